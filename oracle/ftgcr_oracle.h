@@ -1,0 +1,137 @@
+/*
+ * FT-GCR reference oracle (plain C, FP64, serial).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library; it is
+ * not part of the product path.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no source with the
+ * HIP library: the two are written independently from the paper (Gillard &
+ * Benacchio, "FT-GCR: a fault-tolerant generalized conjugate residual elliptic
+ * solver", arXiv 2103.07210) and from the frozen operator readings.
+ *
+ * What it computes
+ *   - the synthetic elliptic operator A (7-point flux-form div(c grad) on a
+ *     lat-lon-height shell, periodic in longitude, zero flux through the poles,
+ *     bottom and top, plus a relative Helmholtz shift), standing in for the
+ *     paper's operator L of Eq. (1);
+ *   - the column preconditioner P (the vertical tridiagonal part of A), solved
+ *     by the Thomas algorithm; the paper only says the solver is
+ *     left-preconditioned for the anisotropy of the domain (Section 2);
+ *   - FT-GCR(k) of Algorithm 1, red (fault tolerance) part included or not,
+ *     with the sign, restart, backup and tie readings listed in the design
+ *     notes, plus a harness-driven bit-flip fault plan.
+ *
+ * Layout: every field is C-order [nz][ny][nx], longitude fastest.  Flat index
+ * of cell (i, j, k) is i + nx*(j + ny*k).
+ *
+ * What pins each function (closed forms, dense solves, library GMRES, predicted
+ * fault outcomes) is listed in the docstring of the Python wrapper,
+ * oracle/oracle.py; the pins themselves are tests/test_oracle_*.py.
+ */
+#ifndef FTGCR_ORACLE_H
+#define FTGCR_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nx, ny, nz;       /* longitudes, latitudes, levels                  */
+    double shell_depth;       /* vertical extent H_s of the shell (unit sphere) */
+    double hill_lon, hill_lat;/* hill centre (radians)                          */
+    double hill_amp;          /* a_h in c = 1 + a_h h g                         */
+    double hill_width;        /* w in h = exp(-(gc/w)^2)                        */
+    double decay_z;           /* g = exp(-zeta/decay_z)                         */
+    double helmholtz;         /* sigma: A = A0 + sigma diag(A0)                 */
+} orc_problem;
+
+/* Face weights of the flux-form operator, all FP64.
+ *   wx[(k*ny + j)*nx + i]       face between cells i and i+1 (periodic)
+ *   wy[(k*(ny+1) + j)*nx + i]   face between latitude rows j-1 and j, j=0..ny
+ *                               (exactly zero for j=0 and j=ny: the poles)
+ *   wz[(k*ny + j)*nx + i]       face between levels k-1 and k, k=0..nz
+ *                               (exactly zero for k=0 and k=nz)
+ * Sizes: nx*ny*nz, nx*(ny+1)*nz, nx*ny*(nz+1).  Caller-owned. */
+void orc_face_weights(const orc_problem* pb, double* wx, double* wy, double* wz);
+
+/* Hill height h(lon, lat) in [0, 1]. */
+double orc_hill(const orc_problem* pb, double lon, double lat);
+
+/* y = A x. */
+void orc_apply_A(const orc_problem* pb, const double* wx, const double* wy,
+                 const double* wz, const double* x, double* y);
+
+/* e = P^{-1} r, P = vertical tridiagonal part of A (one Thomas solve per column). */
+void orc_apply_pinv(const orc_problem* pb, const double* wx, const double* wy,
+                    const double* wz, const double* r, double* e);
+
+/* Plain left-to-right FP64 inner product over n entries. */
+double orc_dot(int64_t n, const double* a, const double* b);
+
+/* One fault event: XOR bit(s) into the IEEE-754 binary64 pattern of entries of
+ * one working vector at the start of executed step `step` (1-based), before
+ * that step reads anything.  idx == NULL means the contiguous range
+ * [start, start+count).  bits == NULL means every entry gets bit `bit`. */
+enum { ORC_V_X = 0, ORC_V_R = 1, ORC_V_P = 2, ORC_V_AP = 3 };
+typedef struct {
+    int64_t step;
+    int32_t vec;
+    int32_t bit;
+    int64_t count;
+    int64_t start;
+    const int64_t* idx;
+    const uint8_t* bits;
+} orc_event;
+
+enum { ORC_CONVERGED = 0, ORC_MAX_STEPS = 1, ORC_STAGNATED = 2, ORC_BREAKDOWN = 3 };
+
+typedef struct {
+    int64_t step;       /* executed step at which the detector fired            */
+    int32_t nu;         /* inner index nu of that step                          */
+    int32_t action;     /* 0 = rolled back, 1 = accepted as stagnation          */
+    double rr_old, rr_new;
+} orc_detect;
+
+typedef struct {
+    int32_t status;
+    int32_t detections;
+    int32_t stagnation_accepts;
+    int32_t events_applied;
+    int64_t steps_executed;
+    int64_t steps_accepted;
+    int64_t steps_wasted;
+    int64_t cycles;              /* number of nu = 0 steps executed              */
+    double rhs_norm2;            /* <R,R>                                        */
+    double rr_final;             /* recursive <r,r> at return                    */
+    double rel_res_recursive;    /* sqrt(rr_final / rhs_norm2)                   */
+    int32_t log_len;
+    int32_t pad_;
+    int64_t hist_len;
+} orc_stats;
+
+/* FT-GCR(k) solve of A x = rhs, x in/out (initial guess in).  Returns 0, or -1
+ * on invalid arguments / allocation failure.  tol is relative on the recursive
+ * residual: stop when <r,r> <= tol^2 <rhs,rhs>.  ft = 0 runs plain GCR(k).
+ * log (log_cap entries) and hist (<r,r> after each executed step, hist_cap
+ * entries) are optional. */
+int orc_solve(const orc_problem* pb, const double* rhs, double* x, double tol,
+              int32_t k, int64_t max_steps, int32_t ft,
+              const orc_event* events, int32_t n_events, orc_stats* st,
+              orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
+
+/* Same, plus optional per-step orthogonality diagnostics (cap entries each,
+ * NULL to skip): cos_r_ap[s-1] = max over l <= nu of |<r^{nu+1}, Lp^l>| /
+ * (|r^{nu+1}| |Lp^l|) after the update of step s, and cos_ap[s-1] = max over
+ * l <= nu of |<Lp^{nu+1}, Lp^l>| / (|Lp^{nu+1}| |Lp^l|) after its new
+ * direction (0 for steps that exit or roll back). */
+int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double tol,
+                     int32_t k, int64_t max_steps, int32_t ft,
+                     const orc_event* events, int32_t n_events, orc_stats* st,
+                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap,
+                     double* cos_r_ap, double* cos_ap, int64_t trace_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
