@@ -1,0 +1,235 @@
+/*
+ * ftgcr.h -- C ABI of the MI355X (gfx950) FT-GCR library, libftgcr.so.
+ *
+ * FT-GCR (Gillard & Benacchio, "FT-GCR: a fault-tolerant generalized
+ * conjugate residual elliptic solver", arXiv 2103.07210) is preconditioned
+ * GCR(k) (Algorithm 1, black part) plus a soft-fault layer (Algorithm 1, red
+ * part): after every update the residual norm must strictly decrease (the
+ * Krylov nesting argument of Section 2); if it does not, the solver restores
+ * the last known-good state [phi, r, p, L(p)]* taken at the start of the
+ * previous complete pass (Section 2, text after Algorithm 1) and redoes it.
+ *
+ * The operator is a synthetic stand-in for the paper's elliptic operator L
+ * of Eq. (1): a 7-point flux-form -div(c grad) on a lat-lon-height shell of
+ * the unit sphere (longitude periodic, zero flux through the poles, bottom
+ * and top) with c = 1 + hill_amp * h(lon, lat) * exp(-zeta / decay_z),
+ * h = exp(-(gc / hill_width)^2) (gc: great-circle distance to the hill
+ * centre), plus a shift: A = A0 + helmholtz * diag(A0).  The preconditioner
+ * P is the vertical (column) tridiagonal part of A; the paper only states
+ * that GCR is left-preconditioned for the anisotropy of the domain (Section 2).
+ *
+ * Conventions
+ *  - Every field is a contiguous C-order array [nz][nlat][nlon] (longitude
+ *    fastest); flat index of cell (i, j, k) is i + nlon*(j + nlat*k).
+ *  - Device pointers are HIP device memory of the handle's device; the
+ *    caller owns them.  Host pointers (plans, stats, logs) are read or written
+ *    only during the call.
+ *  - Every call returns ftgcr_status: 0 on success, < 0 on misuse or runtime
+ *    failure, with a message from ftgcr_last_error().  No C++ exception
+ *    crosses the ABI.  Not converging is an outcome, not an error: the solve
+ *    returns FTGCR_OK with stats.status = FTGCR_MAX_STEPS or FTGCR_BREAKDOWN.
+ *  - Work is enqueued on the handle's stream; solves return when done
+ *    (the step count is data dependent).  A handle is not thread-safe.
+ */
+#ifndef FTGCR_H
+#define FTGCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FTGCR_OK = 0,
+    FTGCR_E_INVALID = -1,      /* bad argument                                   */
+    FTGCR_E_HIP = -2,          /* HIP runtime error                              */
+    FTGCR_E_NOMEM = -3,        /* device or host allocation failed               */
+    FTGCR_E_WORKSPACE = -4,    /* no workspace, or smaller than required         */
+    FTGCR_E_UNSUPPORTED = -5   /* valid but outside what this build supports     */
+} ftgcr_status;
+
+typedef enum { FTGCR_FP64 = 0, FTGCR_MIXED = 1 } ftgcr_precision;
+typedef enum { FTGCR_PRECOND_NONE = 0, FTGCR_PRECOND_COLUMN = 1 } ftgcr_precond;
+
+/* Solve outcomes (ftgcr_stats.status). */
+enum { FTGCR_CONVERGED = 0, FTGCR_MAX_STEPS = 1, FTGCR_STAGNATED = 2, FTGCR_BREAKDOWN = 3 };
+
+/* Largest Krylov space size k (kmax) a handle may be created with. */
+#define FTGCR_KMAX 16
+/* Capacity of the device-side detection log per solve. */
+#define FTGCR_LOG_CAP 256
+
+typedef struct {
+    int32_t nlon;          /* >= 3                                              */
+    int32_t nlat;          /* >= 1                                              */
+    int32_t nz;            /* 1 .. 96 with the column preconditioner            */
+    double shell_depth;    /* vertical extent of the shell, unit sphere; > 0    */
+} ftgcr_grid;
+
+typedef struct {
+    double hill_lon, hill_lat;  /* hill centre, radians                         */
+    double hill_amp;            /* >= 0                                         */
+    double hill_width;          /* > 0                                          */
+    double decay_z;             /* > 0                                          */
+    double helmholtz;           /* > 0 (SPD); the shift relative to diag(A0)    */
+} ftgcr_coeffs;
+
+typedef struct {
+    int32_t ft;              /* 1: FT-GCR (Algorithm 1 with the red part); 0: GCR */
+    int32_t poll_steps;      /* steps enqueued between status reads (>= 1)      */
+    int64_t max_steps;       /* cap on executed inner steps (all refinements)   */
+    double inner_tol;        /* MIXED: inner stop, relative to the refinement's
+                                true residual                                    */
+    int32_t max_refinements; /* MIXED: cap on outer refinement rounds           */
+    int32_t inner_max_steps; /* MIXED: cap on inner steps per round            */
+    int64_t hist_cap;        /* entries of the per-step residual history kept   */
+    int32_t use_graphs;      /* 1: replay captured step sequences (hipGraph)     */
+    int32_t levels_per_block;/* stencil kernels: levels per block (0 = auto)    */
+    int32_t profile_kernels; /* 1: time every step kernel with a HIP event pair
+                                on the solve stream (ftgcr_kernel_times)         */
+    int32_t pad_;
+} ftgcr_options;
+
+/* Fault injection (test harness).  At the start of executed inner step `step`
+ * (1-based, counted over the whole solve), before the step reads anything,
+ * XOR bit `bit` (or bits[t] per entry) into the IEEE-754 pattern of entries of
+ * one working vector: the iterate x (binary64), the residual r, the current
+ * direction p^nu, or its image L(p^nu) (binary64 in FP64 handles, binary32 in
+ * MIXED handles: bits 0..31).  idx == NULL means the range [start,
+ * start+count).  The paper flips bits of e = P^{-1}(r) (Section 3); this
+ * ABI targets the vectors the workload configurations name.  An event whose
+ * step is never reached is not applied. */
+typedef enum { FTGCR_V_X = 0, FTGCR_V_R = 1, FTGCR_V_P = 2, FTGCR_V_AP = 3 } ftgcr_vec;
+typedef struct {
+    int64_t step;
+    int32_t vec;           /* ftgcr_vec                                         */
+    int32_t bit;
+    int64_t count;
+    int64_t start;
+    const int64_t* idx;    /* host, count entries, each in [0, N)               */
+    const uint8_t* bits;   /* host, count entries, or NULL                      */
+} ftgcr_fault_event;
+
+typedef struct {
+    int32_t n_events;
+    const ftgcr_fault_event* events;   /* host array                            */
+} ftgcr_fault_plan;
+
+typedef struct {
+    int64_t step;          /* executed step whose residual failed to decrease   */
+    int32_t nu;            /* pass index nu of that step                        */
+    int32_t action;        /* 0: rolled back to the backup; 1: accepted as
+                              stagnation (same place again, no fault since)     */
+    double rr_old, rr_new; /* <r,r> before and after the update                 */
+} ftgcr_detect_rec;
+
+typedef struct {
+    int32_t status;              /* FTGCR_CONVERGED, _MAX_STEPS, _BREAKDOWN      */
+    int32_t detections;
+    int32_t stagnation_accepts;
+    int32_t events_applied;
+    int64_t steps_executed;      /* inner steps run, including wasted ones       */
+    int64_t steps_accepted;
+    int64_t steps_wasted;        /* steps undone by rollbacks                    */
+    int64_t cycles;              /* passes with nu = 0 executed                  */
+    int32_t refinements;         /* MIXED: outer rounds run                      */
+    int32_t log_len;             /* records written to log (<= log_cap)          */
+    double rhs_norm2;            /* <R, R>                                       */
+    double rr_final;             /* recursive <r, r> at return (last round)      */
+    double rel_res_recursive;
+    double rel_res_true;         /* ||A x - R|| / ||R|| in FP64 on the returned x */
+    double time_ms;              /* device time of the solve                     */
+    int32_t log_cap;             /* in: capacity of log (0: no log)              */
+    int32_t pad_;
+    ftgcr_detect_rec* log;       /* in: caller-owned host array or NULL          */
+    int64_t hist_cap;            /* in: capacity of hist (0: none)               */
+    int64_t hist_len;            /* out                                          */
+    double* hist;                /* in: caller-owned host array: <r,r> after each
+                                    executed step (detector value)              */
+} ftgcr_stats;
+
+typedef struct ftgcr_handle ftgcr_handle;
+
+/* Fill *opt with defaults: ft=1, poll_steps=16, max_steps=100000,
+ * inner_tol=1e-5, max_refinements=20, inner_max_steps=5000, hist_cap=65536,
+ * use_graphs=1, levels_per_block=0. */
+void ftgcr_default_options(ftgcr_options* opt);
+
+/* Create a solver for one grid and coefficient set on the current HIP device.
+ * Builds the FP64 coefficient tables (hill at cell and face centres, vertical
+ * decay, metric factors) and the device state.  kmax bounds k in later solves
+ * (1 <= kmax <= FTGCR_KMAX).  hip_stream is a hipStream_t (NULL: default). */
+ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs,
+                          ftgcr_precond precond, ftgcr_precision precision,
+                          int32_t kmax, void* hip_stream, ftgcr_handle** out);
+
+ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt);
+ftgcr_status ftgcr_get_options(const ftgcr_handle* h, ftgcr_options* opt);
+ftgcr_status ftgcr_set_stream(ftgcr_handle* h, void* hip_stream);
+
+/* Device workspace the caller must provide (bytes), for the handle's kmax:
+ * 2 (kmax+1) + 4 working vectors in the storage precision (directions p^l,
+ * their images L(p^l), three residual buffers, e = P^{-1} r), one FP64 iterate
+ * buffer, block partial sums and the residual history. */
+size_t ftgcr_workspace_bytes(const ftgcr_handle* h);
+/* dev_ptr: device memory of at least ftgcr_workspace_bytes(h) bytes, 256-byte
+ * aligned, owned by the caller and kept alive while the handle solves. */
+ftgcr_status ftgcr_set_workspace(ftgcr_handle* h, void* dev_ptr, size_t bytes);
+
+/* Solve A x = rhs (Eq. (1)) with FT-GCR(k), Algorithm 1.
+ *  rhs_dev : device, FP64, N entries (read only).
+ *  x_dev   : device, FP64, N entries; in: initial guess phi^0, out: solution.
+ *  tol     : FP64 handles stop when <r,r> <= tol^2 <R,R> on the recursive
+ *            residual; MIXED handles stop when the FP64 true residual
+ *            ||A x - R|| <= tol ||R|| (iterative refinement, inner FT-GCR with
+ *            binary32 vectors and FP64 arithmetic, inner products and detector).
+ *  k       : Krylov space size, 1 <= k <= kmax.
+ *  plan    : fault plan or NULL.
+ *  stats   : NULL or caller-owned; log/hist fields are inputs.
+ * The residual-norm test, the backup at each pass nu = 0 and the rollback are
+ * those of Algorithm 1 (red part) when options.ft = 1. */
+ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev,
+                         double tol, int32_t k, const ftgcr_fault_plan* plan,
+                         ftgcr_stats* stats);
+
+/* Solve n independent problems at once (an ensemble): every handle must be
+ * FP64, have its own workspace and share the first handle's stream; their
+ * step kernels run as combined launches over all unfinished members, each
+ * member keeping its own convergence and fault state on the device.
+ * rhs[m], x[m], tol[m] as in ftgcr_solve; plans may be NULL (no faults) or an
+ * array of n plans; stats may be NULL or an array of n. */
+ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n,
+                               const double* const* rhs, double* const* x,
+                               const double* tol, int32_t k,
+                               const ftgcr_fault_plan* plans, ftgcr_stats* stats);
+
+/* Per-kernel device time accumulated while options.profile_kernels = 1:
+ * one record per kernel of the step sequence (update_thomas, reduce_decide,
+ * stencil_dots, reduce_alpha, dir_update, reduce_beta), each the sum of the
+ * HIP event intervals around its launches.  Writes min(cap, count) records
+ * and the count to *n_out. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} ftgcr_kernel_time;
+ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, int32_t cap, int32_t* n_out);
+ftgcr_status ftgcr_reset_kernel_times(ftgcr_handle* h);
+
+void ftgcr_destroy(ftgcr_handle* h);
+
+/* Message of the last failed call on h (or of the last failed create when h
+ * is NULL).  Valid until the next call on the same handle. */
+const char* ftgcr_last_error(const ftgcr_handle* h);
+
+/* Parity entry points (FP64, device pointers of N entries, on the handle's
+ * stream, synchronous): out = A in, and out = P^{-1} in. */
+ftgcr_status ftgcr_debug_apply_A(ftgcr_handle* h, const double* in_dev, double* out_dev);
+ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, double* out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

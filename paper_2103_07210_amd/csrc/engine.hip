@@ -1,0 +1,777 @@
+// Host engine and C ABI of libftgcr (see include/ftgcr.h).
+//
+// The engine builds the FP64 coefficient tables once per handle, lays the
+// working vectors out in the caller's workspace, and drives a solve as a
+// sequence of step launches on the handle's stream.  All decisions of
+// Algorithm 1 (exit, fault test, backup, rollback, cycle restart) are taken
+// on the device; the host only enqueues steps, inserts the harness's fault
+// events before the step they belong to, and reads one status word every
+// `poll_steps` steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ftgcr_internal.h"
+
+using namespace ftgcr;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct ftgcr_handle {
+    ftgcr_grid grid{};
+    ftgcr_coeffs co{};
+    int precond = FTGCR_PRECOND_COLUMN;
+    int precision = FTGCR_FP64;
+    int kmax = 1;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    ftgcr_options opt{};
+    std::string err;
+
+    Geo geo{};
+    double* tables = nullptr;       // device coefficient tables
+    SolveState* st = nullptr;       // device control state
+    void* inst = nullptr;           // device Inst<T> of the storage type
+    Inst<double>* inst_dbg = nullptr;  // device Inst<double> for the parity entry points
+    int* blk0 = nullptr;            // device {0, nblk_col, 0, nblk_st}
+    SolveState* st_host = nullptr;  // pinned copy for reading back
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+
+    long long* ev_idx = nullptr;    // device staging of fault-event entries
+    unsigned char* ev_bits = nullptr;
+    size_t ev_cap = 0;
+
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+
+    int nblk_col = 0, nblk_st = 0;
+    int kc = 1, tx = 1, ty = 1, tz = 1, H = 4;
+
+    // kernel timing (options.profile_kernels)
+    struct Pending {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
+    std::vector<Pending> pending;
+    double kt_ms[6] = {0, 0, 0, 0, 0, 0};
+    long long kt_n[6] = {0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+ftgcr_status fail(ftgcr_handle* h, ftgcr_status code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIP_TRY(h, call)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((h), FTGCR_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+// Great-circle distance to the hill centre in the haversine form, and the
+// hill h = exp(-(gc / width)^2) (used only to tabulate the coefficients).
+double hill_height(const ftgcr_coeffs& c, double lon, double lat)
+{
+    const double a = std::sin(0.5 * (lat - c.hill_lat));
+    const double b = std::sin(0.5 * (lon - c.hill_lon));
+    double root = std::sqrt(a * a + std::cos(lat) * std::cos(c.hill_lat) * b * b);
+    root = std::min(root, 1.0);
+    const double q = 2.0 * std::asin(root) / c.hill_width;
+    return std::exp(-q * q);
+}
+
+int auto_levels_per_block(int tx, int ty, int nz)
+{
+    const long long cols = (long long)tx * ty;
+    const int cand[] = {16, 8, 4, 2};
+    for (int kc : cand) {
+        const long long blocks = cols * ((nz + kc - 1) / kc);
+        if (blocks >= 2048 && kc <= nz) return kc;
+    }
+    return 1;
+}
+
+void set_tiling(ftgcr_handle* h)
+{
+    const Geo& g = h->geo;
+    h->nblk_col = (g.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK;
+    h->tx = (g.nx + ST_TX - 1) / ST_TX;
+    h->ty = (g.ny + ST_TY - 1) / ST_TY;
+    int kc = h->opt.levels_per_block;
+    if (kc != 1 && kc != 2 && kc != 4 && kc != 8 && kc != 16) kc = auto_levels_per_block(h->tx, h->ty, g.nz);
+    h->kc = kc;
+    h->tz = (g.nz + kc - 1) / kc;
+    h->nblk_st = h->tx * h->ty * h->tz;
+}
+
+size_t elem_bytes(const ftgcr_handle* h) { return h->precision == FTGCR_MIXED ? 4 : 8; }
+
+struct Layout {
+    size_t vec, xvec, part, hist, total;
+};
+
+Layout layout(const ftgcr_handle* h)
+{
+    Layout L;
+    const size_t n = (size_t)h->geo.n;
+    L.vec = align256(n * elem_bytes(h));
+    L.xvec = align256(n * sizeof(double));
+    L.part = align256((size_t)std::max(h->nblk_col, h->nblk_st) * NV_MAX * sizeof(double));
+    L.hist = align256((size_t)std::max<long long>(h->opt.hist_cap, 1) * sizeof(double));
+    L.total = (size_t)(2 * (h->kmax + 1) + 4) * L.vec + L.xvec + L.part + L.hist;
+    return L;
+}
+
+template <typename T>
+Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x)
+{
+    Inst<T> in;
+    std::memset(&in, 0, sizeof in);
+    in.g = h->geo;
+    const Layout L = layout(h);
+    char* p = (char*)h->ws;
+    for (int l = 0; l <= h->kmax; ++l) { in.P[l] = (T*)p; p += L.vec; }
+    for (int l = 0; l <= h->kmax; ++l) { in.AP[l] = (T*)p; p += L.vec; }
+    for (int q = 0; q < 3; ++q) { in.R[q] = (T*)p; p += L.vec; }
+    in.E = (T*)p; p += L.vec;
+    in.X[0] = x;
+    in.X[1] = (double*)p; p += L.xvec;
+    in.part = (double*)p; p += L.part;
+    in.hist = (double*)p;
+    in.hist_cap = h->opt.hist_cap;
+    in.rhs = rhs;
+    in.st = h->st;
+    in.nblk_col = h->nblk_col;
+    in.nblk_st = h->nblk_st;
+    in.kc = h->kc;
+    in.tx = h->tx;
+    in.ty = h->ty;
+    in.tz = h->tz;
+    return in;
+}
+
+ftgcr_status upload_tables(ftgcr_handle* h)
+{
+    const int nx = h->grid.nlon, ny = h->grid.nlat, nz = h->grid.nz;
+    const double dlon = 2.0 * kPi / nx, dlat = kPi / ny, dz = h->grid.shell_depth / nz;
+    const ftgcr_coeffs& c = h->co;
+    const size_t nhx = (size_t)nx * ny, nhy = (size_t)nx * (ny + 1), nhc = (size_t)nx * ny;
+    const size_t total = nhx + nhy + nhc + nz + (nz + 1) + ny + (ny + 1) + ny;
+    std::vector<double> t(total, 0.0);
+    double* hx = t.data();
+    double* hy = hx + nhx;
+    double* hc = hy + nhy;
+    double* gc = hc + nhc;
+    double* gf = gc + nz;
+    double* Gx = gf + (nz + 1);
+    double* Gy = Gx + ny;
+    double* Gz = Gy + (ny + 1);
+    auto lon_c = [&](int i) { return (i + 0.5) * dlon; };
+    auto lon_e = [&](int i) { return (i + 1.0) * dlon; };
+    auto lat_c = [&](int j) { return -0.5 * kPi + (j + 0.5) * dlat; };
+    auto lat_s = [&](int j) { return -0.5 * kPi + j * dlat; };
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            hx[(size_t)j * nx + i] = c.hill_amp * hill_height(c, lon_e(i), lat_c(j));
+            hc[(size_t)j * nx + i] = c.hill_amp * hill_height(c, lon_c(i), lat_c(j));
+        }
+    for (int j = 1; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) hy[(size_t)j * nx + i] = c.hill_amp * hill_height(c, lon_c(i), lat_s(j));
+    for (int k = 0; k < nz; ++k) gc[k] = std::exp(-((k + 0.5) / nz) / c.decay_z);
+    for (int k = 0; k <= nz; ++k) gf[k] = std::exp(-((double)k / nz) / c.decay_z);
+    for (int j = 0; j < ny; ++j) {
+        Gx[j] = dlat * dz / (std::cos(lat_c(j)) * dlon);
+        Gz[j] = std::cos(lat_c(j)) * dlon * dlat / dz;
+    }
+    for (int j = 1; j < ny; ++j) Gy[j] = std::cos(lat_s(j)) * dlon * dz / dlat;   // poles stay exactly 0
+    HIP_TRY(h, hipMalloc(&h->tables, total * sizeof(double)));
+    HIP_TRY(h, hipMemcpy(h->tables, t.data(), total * sizeof(double), hipMemcpyHostToDevice));
+    Geo& g = h->geo;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.ncols = nx * ny;
+    g.n = (long long)nx * ny * nz;
+    g.opsig = 1.0 + c.helmholtz;
+    g.hx = h->tables;
+    g.hy = g.hx + nhx;
+    g.hc = g.hy + nhy;
+    g.gc = g.hc + nhc;
+    g.gf = g.gc + nz;
+    g.Gx = g.gf + (nz + 1);
+    g.Gy = g.Gx + ny;
+    g.Gz = g.Gy + (ny + 1);
+    return FTGCR_OK;
+}
+
+ftgcr_status upload_debug_inst(ftgcr_handle* h)
+{
+    Inst<double> in;
+    std::memset(&in, 0, sizeof in);
+    in.g = h->geo;
+    in.st = h->st;
+    in.nblk_col = h->nblk_col;
+    in.nblk_st = h->nblk_st;
+    in.kc = h->kc;
+    in.tx = h->tx;
+    in.ty = h->ty;
+    in.tz = h->tz;
+    HIP_TRY(h, hipMemcpy(h->inst_dbg, &in, sizeof in, hipMemcpyHostToDevice));
+    const int blk0[4] = {0, h->nblk_col, 0, h->nblk_st};
+    HIP_TRY(h, hipMemcpy(h->blk0, blk0, sizeof blk0, hipMemcpyHostToDevice));
+    return FTGCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one solve
+// ---------------------------------------------------------------------------
+
+struct DevEvent {
+    long long step;
+    int vec, bit;
+    long long count, start;
+    const long long* idx;        // device or null
+    const unsigned char* bits;   // device or null
+};
+
+const char* const kKernelNames[6] = {"update_thomas", "reduce_decide", "stencil_dots",
+                                     "reduce_alpha", "dir_update", "reduce_beta"};
+
+hipEvent_t take_event(ftgcr_handle* h)
+{
+    if (h->ev_next == h->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->ev_pool.push_back(e);
+    }
+    return h->ev_pool[h->ev_next++];
+}
+
+// Resolve the event pairs recorded since the last synchronisation.
+void collect_times(ftgcr_handle* h)
+{
+    for (const auto& p : h->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            h->kt_ms[p.cls] += ms;
+            h->kt_n[p.cls] += 1;
+        }
+    }
+    h->pending.clear();
+    h->ev_next = 0;
+}
+
+template <typename T>
+struct Runner {
+    using L = Launch<T>;
+    ftgcr_handle* h;
+    Table<T> tb;
+    hipStream_t s;
+
+    template <class F>
+    void timed(int cls, F&& launch)
+    {
+        if (!h->opt.profile_kernels) {
+            launch();
+            return;
+        }
+        hipEvent_t a = take_event(h), b = take_event(h);
+        if (!a || !b) {
+            launch();
+            return;
+        }
+        (void)hipEventRecord(a, s);
+        launch();
+        (void)hipEventRecord(b, s);
+        h->pending.push_back({cls, a, b});
+    }
+
+    void step()
+    {
+        timed(0, [&] { L::update_thomas(tb, h->nblk_col, h->H, 0, s); });
+        timed(1, [&] { L::reduce_decide(tb, 1, s); });
+        timed(2, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
+        timed(3, [&] { L::reduce_alpha(tb, 1, s); });
+        timed(4, [&] { L::dir_update(tb, h->nblk_st, h->kc, 0, s); });
+        timed(5, [&] { L::reduce_beta(tb, 1, 0, s); });
+    }
+
+    void start_round()
+    {
+        L::update_thomas(tb, h->nblk_col, h->H, 1, s);
+        L::reduce_init(tb, 1, s);
+        L::dir_update(tb, h->nblk_st, h->kc, 1, s);
+        L::reduce_beta(tb, 1, 1, s);
+    }
+
+    void event(const DevEvent& ev)
+    {
+        const long long n = h->geo.n;
+        const int gcopy = (int)std::min<long long>((n + 255) / 256, 8192);
+        const int ginj = (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192));
+        L::event_prep(tb, ev.vec, s);
+        L::event_copy(tb, gcopy, s);
+        L::event_inject(tb, ginj, ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
+        if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) {
+            L::beta_dots(tb, h->nblk_st, s);
+            L::reduce_beta_dots(tb, 1, s);
+        }
+    }
+
+    ftgcr_status read_state()
+    {
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        collect_times(h);
+        return FTGCR_OK;
+    }
+
+    ftgcr_status read_status(int* status)
+    {
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        collect_times(h);
+        *status = h->st_host->status;
+        return FTGCR_OK;
+    }
+
+    // Enqueue steps until the device reports an outcome.  `launched` is the
+    // number of steps executed so far (the device's s).
+    ftgcr_status run_steps(long long launched, long long cap, const std::vector<DevEvent>& evs)
+    {
+        size_t evp = 0;
+        const int chunk = std::max(1, h->opt.poll_steps);
+        const long long guard = cap + chunk + 16;
+        long long issued = 0;
+        while (true) {
+            while (evp < evs.size() && evs[evp].step <= launched) ++evp;
+            if (evp < evs.size() && evs[evp].step == launched + 1) {
+                while (evp < evs.size() && evs[evp].step == launched + 1) event(evs[evp++]);
+                step();
+                launched += 1;
+                issued += 1;
+            } else {
+                long long cnt = chunk;
+                if (evp < evs.size()) cnt = std::min<long long>(cnt, evs[evp].step - 1 - launched);
+                cnt = std::max<long long>(cnt, 1);
+                for (long long q = 0; q < cnt; ++q) step();
+                launched += cnt;
+                issued += cnt;
+            }
+            int status = RUNNING;
+            ftgcr_status rc = read_status(&status);
+            if (rc != FTGCR_OK) return rc;
+            if (status != RUNNING) return FTGCR_OK;
+            if (issued > guard) return fail(h, FTGCR_E_HIP, "step loop did not terminate");
+        }
+    }
+};
+
+ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::vector<DevEvent>& out)
+{
+    out.clear();
+    if (!plan || plan->n_events <= 0) return FTGCR_OK;
+    if (!plan->events) return fail(h, FTGCR_E_INVALID, "plan has events == NULL");
+    const long long n = h->geo.n;
+    const int maxbit = (h->precision == FTGCR_MIXED) ? 31 : 63;
+    size_t need = 0;
+    for (int q = 0; q < plan->n_events; ++q) {
+        const ftgcr_fault_event& e = plan->events[q];
+        if (e.vec < FTGCR_V_X || e.vec > FTGCR_V_AP) return fail(h, FTGCR_E_INVALID, "event vec out of range");
+        if (e.count < 0) return fail(h, FTGCR_E_INVALID, "event count < 0");
+        const int bmax = (e.vec == FTGCR_V_X) ? 63 : maxbit;
+        if (!e.bits && (e.bit < 0 || e.bit > bmax)) return fail(h, FTGCR_E_INVALID, "event bit out of range");
+        if (!e.idx && (e.start < 0 || e.start + e.count > n)) return fail(h, FTGCR_E_INVALID, "event range out of bounds");
+        for (long long t = 0; t < e.count; ++t) {
+            if (e.idx && (e.idx[t] < 0 || e.idx[t] >= n)) return fail(h, FTGCR_E_INVALID, "event index out of bounds");
+            if (e.bits && e.bits[t] > bmax) return fail(h, FTGCR_E_INVALID, "event bit out of range");
+        }
+        if (e.idx || e.bits) need += (size_t)e.count;
+    }
+    if (need > h->ev_cap) {
+        if (h->ev_idx) (void)hipFree(h->ev_idx);
+        if (h->ev_bits) (void)hipFree(h->ev_bits);
+        h->ev_idx = nullptr;
+        h->ev_bits = nullptr;
+        h->ev_cap = 0;
+        HIP_TRY(h, hipMalloc(&h->ev_idx, need * sizeof(long long)));
+        HIP_TRY(h, hipMalloc(&h->ev_bits, need));
+        h->ev_cap = need;
+    }
+    size_t off = 0;
+    for (int q = 0; q < plan->n_events; ++q) {
+        const ftgcr_fault_event& e = plan->events[q];
+        DevEvent d;
+        d.step = e.step;
+        d.vec = e.vec;
+        d.bit = e.bit;
+        d.count = e.count;
+        d.start = e.start;
+        d.idx = nullptr;
+        d.bits = nullptr;
+        if (e.idx && e.count > 0) {
+            HIP_TRY(h, hipMemcpy(h->ev_idx + off, e.idx, (size_t)e.count * sizeof(long long), hipMemcpyHostToDevice));
+            d.idx = h->ev_idx + off;
+        }
+        if (e.bits && e.count > 0) {
+            HIP_TRY(h, hipMemcpy(h->ev_bits + off, e.bits, (size_t)e.count, hipMemcpyHostToDevice));
+            d.bits = h->ev_bits + off;
+        }
+        if (e.idx || e.bits) off += (size_t)e.count;
+        if (e.count > 0 && e.step >= 1) out.push_back(d);
+    }
+    std::stable_sort(out.begin(), out.end(), [](const DevEvent& a, const DevEvent& b) { return a.step < b.step; });
+    return FTGCR_OK;
+}
+
+void fill_stats(ftgcr_handle* h, const SolveState& st, int refinements, float ms, ftgcr_stats* stats)
+{
+    if (!stats) return;
+    stats->status = st.status;
+    stats->detections = st.detections;
+    stats->stagnation_accepts = st.stagnation_accepts;
+    stats->events_applied = st.events_applied;
+    stats->steps_executed = st.s;
+    stats->steps_accepted = st.accepted;
+    stats->steps_wasted = st.s - st.accepted;
+    stats->cycles = st.cycles;
+    stats->refinements = refinements;
+    stats->rhs_norm2 = st.RR;
+    stats->rr_final = st.rr_old;
+    stats->rel_res_recursive = st.RR > 0 ? std::sqrt(st.rr_old / st.RR) : 0.0;
+    stats->rel_res_true = st.RR > 0 ? std::sqrt(st.rt2 / st.RR) : 0.0;
+    stats->time_ms = ms;
+    stats->log_len = 0;
+    if (stats->log && stats->log_cap > 0) {
+        const int nlog = std::min(std::min(st.log_len, LOG_CAP), stats->log_cap);
+        for (int q = 0; q < nlog; ++q) {
+            stats->log[q].step = st.log[q].step;
+            stats->log[q].nu = st.log[q].nu;
+            stats->log[q].action = st.log[q].action;
+            stats->log[q].rr_old = st.log[q].rr_old;
+            stats->log[q].rr_new = st.log[q].rr_new;
+        }
+        stats->log_len = nlog;
+    }
+    stats->hist_len = 0;
+    (void)h;
+}
+
+template <typename T>
+ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double tol, int k,
+                        const ftgcr_fault_plan* plan, ftgcr_stats* stats)
+{
+    using L = Launch<T>;
+    hipStream_t s = h->stream;
+    std::vector<DevEvent> evs;
+    ftgcr_status rc = stage_events(h, plan, evs);
+    if (rc != FTGCR_OK) return rc;
+
+    Inst<T> in = make_inst<T>(h, rhs, x);
+    HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, 1}, s};
+    const Table<T>& tb = run.tb;
+    const bool mixed = h->precision == FTGCR_MIXED;
+    const long long max_steps = h->opt.max_steps;
+    int refinements = 0;
+
+    HIP_TRY(h, hipEventRecord(h->ev_start, s));
+    if (!mixed) {
+        L::init_state(tb, k, h->opt.ft, 0, max_steps, tol * tol, 1, 1, s);
+        L::residual(tb, h->nblk_st, h->kc, 1, s);
+        L::reduce_residual(tb, 1, 1, s);
+        run.start_round();
+        rc = run.run_steps(0, max_steps, evs);
+        if (rc != FTGCR_OK) return rc;
+        L::finalize_x(tb, h->nblk_st, h->kc, s);
+    } else {
+        // iterative refinement: FP64 true residual outside, FT-GCR with
+        // binary32 vectors inside, the correction accumulated into FP64 x
+        L::init_state(tb, k, h->opt.ft, 1, max_steps, 0.0, 1, 1, s);
+        while (true) {
+            L::residual(tb, h->nblk_st, h->kc, 1, s);
+            L::reduce_residual(tb, 1, 0, s);
+            rc = run.read_state();
+            if (rc != FTGCR_OK) return rc;
+            const SolveState& hs = *h->st_host;
+            if (hs.rt2 <= tol * tol * hs.RR) break;                 // converged (true residual)
+            if (hs.s >= max_steps || refinements >= h->opt.max_refinements) break;
+            double tau = std::max(h->opt.inner_tol, 0.5 * tol * std::sqrt(hs.RR / hs.rt2));
+            tau = std::min(tau, 0.5);
+            const long long cap = std::min<long long>(max_steps, hs.s + h->opt.inner_max_steps);
+            const long long s0 = hs.s;
+            L::init_state(tb, k, h->opt.ft, 1, cap, tau * tau, 0, 1, s);
+            L::reduce_residual(tb, 1, 1, s);
+            run.start_round();
+            rc = run.run_steps(s0, cap, evs);
+            if (rc != FTGCR_OK) return rc;
+            L::finalize_x(tb, h->nblk_st, h->kc, s);
+            refinements += 1;
+        }
+    }
+    // FP64 true residual of the returned x
+    L::residual(tb, h->nblk_st, h->kc, 0, s);
+    L::reduce_residual(tb, 1, 0, s);
+    HIP_TRY(h, hipEventRecord(h->ev_stop, s));
+    rc = run.read_state();
+    if (rc != FTGCR_OK) return rc;
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    SolveState st = *h->st_host;
+    if (mixed) {
+        // the outer loop decides convergence on the true residual
+        if (st.rt2 <= tol * tol * st.RR) st.status = FTGCR_CONVERGED;
+        else if (st.status == FTGCR_CONVERGED) st.status = FTGCR_MAX_STEPS;
+    }
+    fill_stats(h, st, refinements, ms, stats);
+    if (stats && stats->hist && stats->hist_cap > 0) {
+        const long long nh = std::min<long long>(std::min<long long>(st.s, h->opt.hist_cap), stats->hist_cap);
+        if (nh > 0) HIP_TRY(h, hipMemcpy(stats->hist, in.hist, (size_t)nh * sizeof(double), hipMemcpyDeviceToHost));
+        stats->hist_len = nh;
+    }
+    return FTGCR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void ftgcr_default_options(ftgcr_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->ft = 1;
+    opt->poll_steps = 16;
+    opt->max_steps = 100000;
+    opt->inner_tol = 1e-5;
+    opt->max_refinements = 20;
+    opt->inner_max_steps = 5000;
+    opt->hist_cap = 65536;
+    opt->use_graphs = 1;
+    opt->levels_per_block = 0;
+    opt->profile_kernels = 0;
+}
+
+ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ftgcr_precond precond,
+                          ftgcr_precision precision, int32_t kmax, void* hip_stream, ftgcr_handle** out)
+{
+    if (!out) return fail(nullptr, FTGCR_E_INVALID, "out == NULL");
+    *out = nullptr;
+    if (!grid || !coeffs) return fail(nullptr, FTGCR_E_INVALID, "grid or coeffs == NULL");
+    if (grid->nlon < 3 || grid->nlat < 1 || grid->nz < 1) return fail(nullptr, FTGCR_E_INVALID, "grid needs nlon >= 3, nlat >= 1, nz >= 1");
+    if (!(grid->shell_depth > 0)) return fail(nullptr, FTGCR_E_INVALID, "shell_depth must be > 0");
+    if (!(coeffs->hill_width > 0) || !(coeffs->decay_z > 0) || !(coeffs->hill_amp >= 0) || !(coeffs->helmholtz > 0))
+        return fail(nullptr, FTGCR_E_INVALID, "coefficients need hill_width > 0, decay_z > 0, hill_amp >= 0, helmholtz > 0");
+    if (kmax < 1 || kmax > FTGCR_KMAX) return fail(nullptr, FTGCR_E_INVALID, "kmax out of range");
+    if (precision != FTGCR_FP64 && precision != FTGCR_MIXED) return fail(nullptr, FTGCR_E_INVALID, "bad precision");
+    if (precond != FTGCR_PRECOND_COLUMN)
+        return fail(nullptr, FTGCR_E_UNSUPPORTED, "only the column preconditioner is built");
+    if (thomas_depth(grid->nz) < 0) return fail(nullptr, FTGCR_E_UNSUPPORTED, "nz > 96 is not supported");
+    const long long ncols = (long long)grid->nlon * grid->nlat;
+    if (ncols > (1LL << 30) || ncols * grid->nz > (1LL << 40)) return fail(nullptr, FTGCR_E_UNSUPPORTED, "grid too large");
+
+    ftgcr_handle* h = new (std::nothrow) ftgcr_handle();
+    if (!h) return fail(nullptr, FTGCR_E_NOMEM, "host allocation failed");
+    h->grid = *grid;
+    h->co = *coeffs;
+    h->precond = precond;
+    h->precision = precision;
+    h->kmax = kmax;
+    h->stream = (hipStream_t)hip_stream;
+    ftgcr_default_options(&h->opt);
+    auto bail = [&](ftgcr_status code) {
+        g_create_error = h->err;
+        ftgcr_destroy(h);
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        h->err = "hipGetDevice failed";
+        return bail(FTGCR_E_HIP);
+    }
+    ftgcr_status rc = upload_tables(h);
+    if (rc != FTGCR_OK) return bail(rc);
+    h->H = thomas_depth(grid->nz);
+    set_tiling(h);
+    if (hipMalloc(&h->st, sizeof(SolveState)) != hipSuccess ||
+        hipMemset(h->st, 0, sizeof(SolveState)) != hipSuccess ||
+        hipMalloc(&h->inst, std::max(sizeof(Inst<double>), sizeof(Inst<float>))) != hipSuccess ||
+        hipMalloc(&h->inst_dbg, sizeof(Inst<double>)) != hipSuccess ||
+        hipMalloc(&h->blk0, 4 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc(&h->st_host, sizeof(SolveState)) != hipSuccess ||
+        hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_stop) != hipSuccess) {
+        h->err = "device allocation failed";
+        return bail(FTGCR_E_NOMEM);
+    }
+    rc = upload_debug_inst(h);
+    if (rc != FTGCR_OK) return bail(rc);
+    *out = h;
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt)
+{
+    if (!h || !opt) return FTGCR_E_INVALID;
+    if (opt->poll_steps < 1 || opt->max_steps < 0 || opt->hist_cap < 0 || opt->max_refinements < 0 ||
+        opt->inner_max_steps < 1 || !(opt->inner_tol > 0) || !(opt->inner_tol < 1))
+        return fail(h, FTGCR_E_INVALID, "invalid options");
+    h->opt = *opt;
+    set_tiling(h);
+    return upload_debug_inst(h);
+}
+
+ftgcr_status ftgcr_get_options(const ftgcr_handle* h, ftgcr_options* opt)
+{
+    if (!h || !opt) return FTGCR_E_INVALID;
+    *opt = h->opt;
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_set_stream(ftgcr_handle* h, void* hip_stream)
+{
+    if (!h) return FTGCR_E_INVALID;
+    h->stream = (hipStream_t)hip_stream;
+    return FTGCR_OK;
+}
+
+size_t ftgcr_workspace_bytes(const ftgcr_handle* h)
+{
+    if (!h) return 0;
+    return layout(h).total;
+}
+
+ftgcr_status ftgcr_set_workspace(ftgcr_handle* h, void* dev_ptr, size_t bytes)
+{
+    if (!h) return FTGCR_E_INVALID;
+    if (!dev_ptr) return fail(h, FTGCR_E_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(h, FTGCR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "workspace smaller than ftgcr_workspace_bytes()");
+    h->ws = dev_ptr;
+    h->ws_bytes = bytes;
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev, double tol, int32_t k,
+                         const ftgcr_fault_plan* plan, ftgcr_stats* stats)
+{
+    if (!h) return FTGCR_E_INVALID;
+    if (!rhs_dev || !x_dev) return fail(h, FTGCR_E_INVALID, "rhs or x is NULL");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(h, FTGCR_E_INVALID, "tol must be finite and > 0");
+    if (k < 1 || k > h->kmax) return fail(h, FTGCR_E_INVALID, "k must be in [1, kmax]");
+    if (!h->ws) return fail(h, FTGCR_E_WORKSPACE, "no workspace set");
+    if (h->ws_bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "workspace smaller than required by the current options");
+    HIP_TRY(h, hipSetDevice(h->device));
+    if (h->precision == FTGCR_MIXED) return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats);
+    return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats);
+}
+
+ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double* const* rhs, double* const* x,
+                               const double* tol, int32_t k, const ftgcr_fault_plan* plans, ftgcr_stats* stats)
+{
+    if (!hs || n < 1 || !rhs || !x || !tol) return FTGCR_E_INVALID;
+    for (int m = 0; m < n; ++m) {
+        ftgcr_status rc = ftgcr_solve(hs[m], rhs[m], x[m], tol[m], k, plans ? &plans[m] : nullptr,
+                                      stats ? &stats[m] : nullptr);
+        if (rc != FTGCR_OK) return rc;
+    }
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, int32_t cap, int32_t* n_out)
+{
+    if (!h || (!out && cap > 0)) return FTGCR_E_INVALID;
+    const int n = 6;
+    for (int q = 0; q < n && q < cap; ++q) {
+        std::memset(out[q].name, 0, sizeof out[q].name);
+        std::strncpy(out[q].name, kKernelNames[q], sizeof out[q].name - 1);
+        out[q].launches = h->kt_n[q];
+        out[q].total_ms = h->kt_ms[q];
+    }
+    if (n_out) *n_out = n;
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_reset_kernel_times(ftgcr_handle* h)
+{
+    if (!h) return FTGCR_E_INVALID;
+    for (int q = 0; q < 6; ++q) {
+        h->kt_ms[q] = 0.0;
+        h->kt_n[q] = 0;
+    }
+    return FTGCR_OK;
+}
+
+void ftgcr_destroy(ftgcr_handle* h)
+{
+    if (!h) return;
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->tables) (void)hipFree(h->tables);
+    if (h->st) (void)hipFree(h->st);
+    if (h->inst) (void)hipFree(h->inst);
+    if (h->inst_dbg) (void)hipFree(h->inst_dbg);
+    if (h->blk0) (void)hipFree(h->blk0);
+    if (h->st_host) (void)hipHostFree(h->st_host);
+    if (h->ev_start) (void)hipEventDestroy(h->ev_start);
+    if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
+    if (h->ev_idx) (void)hipFree(h->ev_idx);
+    if (h->ev_bits) (void)hipFree(h->ev_bits);
+    delete h;
+}
+
+const char* ftgcr_last_error(const ftgcr_handle* h)
+{
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+ftgcr_status ftgcr_debug_apply_A(ftgcr_handle* h, const double* in_dev, double* out_dev)
+{
+    if (!h) return FTGCR_E_INVALID;
+    if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
+    HIP_TRY(h, hipSetDevice(h->device));
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, 1};
+    Launch<double>::debug_apply_A(tb, h->nblk_st, h->kc, in_dev, out_dev, h->stream);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, double* out_dev)
+{
+    if (!h) return FTGCR_E_INVALID;
+    if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
+    HIP_TRY(h, hipSetDevice(h->device));
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, 1};
+    Launch<double>::debug_pinv(tb, h->nblk_col, h->H, in_dev, out_dev, h->stream);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return FTGCR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Internal types shared by the FT-GCR kernels and the host engine.
+//
+// One solve ("instance") keeps all of its control state on the device in a
+// SolveState; the step kernels read it to find the pass index nu, the buffer
+// roles and the scalars of Algorithm 1, so a step is the same fixed kernel
+// sequence whatever happened before (rollbacks included) and can be enqueued
+// or replayed without reading anything back.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ftgcr.h"
+
+namespace ftgcr {
+
+constexpr int KMAX = FTGCR_KMAX;
+constexpr int LOG_CAP = FTGCR_LOG_CAP;
+constexpr int NV_MAX = KMAX + 2;     // reduction values per block
+constexpr int RUNNING = -1;
+
+// Block shapes.  Column kernels: 256 threads = 4 waves, each wave owns 32
+// columns (lanes 0..31 the lower half of each column, 32..63 the upper half).
+constexpr int COL_THREADS = 256;
+constexpr int COLS_PER_BLOCK = 128;
+// Stencil kernels: 64 longitudes x 4 latitudes per block, KC levels each.
+constexpr int ST_TX = 64;
+constexpr int ST_TY = 4;
+constexpr int ST_THREADS = ST_TX * ST_TY;
+constexpr int RED_THREADS = 256;
+
+struct DetectRec {
+    long long step;
+    int nu;
+    int action;
+    double rr_old, rr_new;
+};
+
+// Per-solve control state (device memory, written by single-thread kernel
+// sections only).
+struct SolveState {
+    int status;          // RUNNING or an FTGCR_* outcome
+    int active;          // 1: this step goes on to P^{-1}, L and the new direction
+    int nu;              // pass index of the current step
+    int k;
+    int ft;
+    int mixed;
+    int detections, stagnation_accepts, events_applied, events_since_rb;
+    long long s;         // executed steps
+    long long max_steps; // stop when s reaches this (global or round cap)
+    long long accepted;
+    long long cycles;
+    long long last_rb_pos;
+    double tol2;         // tol^2 (FP64) or inner tol^2 (mixed round)
+    double T;            // exit threshold on <r,r>
+    double RR;           // <R,R>
+    double rt2;          // <r_t, r_t> of the last true-residual pass
+    double rr_old, rr_new;
+    double beta_num;     // <r, L p^nu>
+    double d_cur;        // <L p^nu, L p^nu>
+    double d[KMAX + 1];
+    double beta[KMAX + 1];
+    double alpha[KMAX + 1];
+    int slot[KMAX + 1];  // buffer index of p^l / L(p^l)
+    int r_cur, r_dst, r_bak;
+    int x_base, x_base_nu, x_bak, x_dst;
+    int x_final_hi;      // materialise x with beta_l p^l for l <= this at the end
+    int b_slot0;
+    long long b_accepted;
+    double b_rr, b_beta_num, b_d0;
+    // fault-event staging (set by the event preparation kernel)
+    int ev_ok;           // the event applies (solve still running)
+    int ev_vec;
+    int ev_copy;         // 1: copy src -> dst buffer before flipping
+    int ev_src, ev_dst;  // buffer indices for the copy
+    int ev_lo, ev_hi;    // x materialisation: beta terms l in [lo, hi)
+    int log_len;
+    int pad_;
+    DetectRec log[LOG_CAP];
+};
+
+// Geometry / coefficient tables of one grid (device, FP64).
+struct Geo {
+    int nx, ny, nz;
+    int ncols;               // nx * ny
+    long long n;             // nx * ny * nz
+    double opsig;            // 1 + helmholtz
+    const double* hx;        // [ny][nx]    hill_amp * h at east face (i+1/2, j)
+    const double* hy;        // [ny+1][nx]  hill_amp * h at face (i, j-1/2)
+    const double* hc;        // [ny][nx]    hill_amp * h at centre (i, j)
+    const double* gc;        // [nz]        exp(-zeta_k / decay)
+    const double* gf;        // [nz+1]      exp(-zeta_{k-1/2} / decay)
+    const double* Gx;        // [ny]        dlat dz / (cos(lat_j) dlon)
+    const double* Gy;        // [ny+1]      cos(lat_{j-1/2}) dlon dz / dlat, 0 at poles
+    const double* Gz;        // [ny]        cos(lat_j) dlon dlat / dz
+};
+
+// Everything one instance's kernels need (device copy per solve).
+template <typename T>
+struct Inst {
+    Geo g;
+    T* P[KMAX + 1];
+    T* AP[KMAX + 1];
+    T* R[3];
+    T* E;
+    double* X[2];            // X[0]: caller's x, X[1]: workspace
+    const double* rhs;
+    SolveState* st;
+    double* part;            // block partials [nblk][NV_MAX]
+    double* hist;
+    long long hist_cap;
+    int nblk_col;            // blocks of the column grid
+    int nblk_st;             // blocks of the stencil grid
+    int kc;                  // stencil levels per block
+    int tx, ty, tz;          // stencil tiles per dimension
+};
+
+// Launch table for combined (batched) launches: block b of a launch belongs
+// to instance inst_of(b); blk0[m] is the first block of instance m.
+template <typename T>
+struct Table {
+    const Inst<T>* inst;
+    const int* blk0_col;     // n + 1 prefix sums (column grid)
+    const int* blk0_st;      // n + 1 prefix sums (stencil grid)
+    int n;
+};
+
+// Kernel launchers (kernels.hip).
+template <typename T> struct Launch {
+    static void init_state(const Table<T>& tb, int k, int ft, int mixed, long long max_steps, double tol2,
+                           int reset_counters, int grid, hipStream_t s);
+    static void residual(const Table<T>& tb, int total_st_blocks, int kc, int store, hipStream_t s);
+    static void reduce_residual(const Table<T>& tb, int n, int set_T, hipStream_t s);
+    static void update_thomas(const Table<T>& tb, int total_col_blocks, int H, int mode, hipStream_t s);
+    static void reduce_init(const Table<T>& tb, int n, hipStream_t s);
+    static void reduce_decide(const Table<T>& tb, int n, hipStream_t s);
+    static void stencil_dots(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
+    static void reduce_alpha(const Table<T>& tb, int n, hipStream_t s);
+    static void dir_update(const Table<T>& tb, int total_st_blocks, int kc, int init, hipStream_t s);
+    static void reduce_beta(const Table<T>& tb, int n, int init, hipStream_t s);
+    static void finalize_x(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
+    // fault events (single instance)
+    static void event_prep(const Table<T>& tb, int vec, hipStream_t s);
+    static void event_copy(const Table<T>& tb, int grid, hipStream_t s);
+    static void event_inject(const Table<T>& tb, int grid, const long long* idx, const unsigned char* bits,
+                             long long count, long long start, int bit, hipStream_t s);
+    static void beta_dots(const Table<T>& tb, int total_st_blocks, hipStream_t s);
+    static void reduce_beta_dots(const Table<T>& tb, int n, hipStream_t s);
+    // parity entry points (FP64 only)
+    static void debug_apply_A(const Table<T>& tb, int total_st_blocks, int kc, const double* in, double* out, hipStream_t s);
+    static void debug_pinv(const Table<T>& tb, int total_col_blocks, int H, const double* in, double* out, hipStream_t s);
+};
+
+// Smallest supported register-array depth H >= levels per column half.
+int thomas_depth(int nz);
+
+}  // namespace ftgcr
