@@ -206,9 +206,9 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n,
                                const ftgcr_fault_plan* plans, ftgcr_stats* stats);
 
 /* Per-kernel device time accumulated while options.profile_kernels = 1:
- * one record per kernel of the step sequence (update_thomas, reduce_decide,
- * stencil_dots, reduce_alpha, dir_update, reduce_beta), each the sum of the
- * HIP event intervals around its launches.  Writes min(cap, count) records
+ * one record per kernel of the step sequence (update_thomas, stencil_dots,
+ * dir_update), each the sum of the HIP event intervals around its launches
+ * (launches enqueued after the solve ended are not counted).  Writes min(cap, count) records
  * and the count to *n_out. */
 typedef struct {
     char name[32];

@@ -71,8 +71,8 @@ struct ftgcr_handle {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     std::vector<Pending> pending;
-    double kt_ms[6] = {0, 0, 0, 0, 0, 0};
-    long long kt_n[6] = {0, 0, 0, 0, 0, 0};
+    double kt_ms[3] = {0, 0, 0};
+    long long kt_n[3] = {0, 0, 0};
 };
 
 namespace {
@@ -257,8 +257,7 @@ struct DevEvent {
     const unsigned char* bits;   // device or null
 };
 
-const char* const kKernelNames[6] = {"update_thomas", "reduce_decide", "stencil_dots",
-                                     "reduce_alpha", "dir_update", "reduce_beta"};
+const char* const kKernelNames[3] = {"update_thomas", "stencil_dots", "dir_update"};
 
 hipEvent_t take_event(ftgcr_handle* h)
 {
@@ -318,19 +317,19 @@ struct Runner {
     {
         cur_step = number;
         timed(0, [&] { L::update_thomas(tb, h->nblk_col, h->H, 0, s); });
-        timed(1, [&] { L::reduce_decide(tb, 1, s); });
-        timed(2, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
-        timed(3, [&] { L::reduce_alpha(tb, 1, s); });
-        timed(4, [&] { L::dir_update(tb, h->nblk_st, h->kc, 0, s); });
-        timed(5, [&] { L::reduce_beta(tb, 1, 0, s); });
+        L::finish_col(tb, 0, s);
+        timed(1, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
+        L::finish_alpha(tb, s);
+        timed(2, [&] { L::dir_update(tb, h->nblk_st, h->kc, 0, s); });
+        L::finish_beta(tb, 0, s);
     }
 
     void start_round()
     {
         L::update_thomas(tb, h->nblk_col, h->H, 1, s);
-        L::reduce_init(tb, 1, s);
+        L::finish_col(tb, 1, s);
         L::dir_update(tb, h->nblk_st, h->kc, 1, s);
-        L::reduce_beta(tb, 1, 1, s);
+        L::finish_beta(tb, 1, s);
     }
 
     void event(const DevEvent& ev)
@@ -343,7 +342,6 @@ struct Runner {
         L::event_inject(tb, ginj, ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
         if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) {
             L::beta_dots(tb, h->nblk_st, s);
-            L::reduce_beta_dots(tb, 1, s);
         }
     }
 
@@ -511,8 +509,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     HIP_TRY(h, hipEventRecord(h->ev_start, s));
     if (!mixed) {
         L::init_state(tb, k, h->opt.ft, 0, max_steps, tol * tol, 1, 1, s);
-        L::residual(tb, h->nblk_st, h->kc, 1, s);
-        L::reduce_residual(tb, 1, 1, s);
+        L::residual(tb, h->nblk_st, h->kc, 1, 1, s);
         run.start_round();
         rc = run.run_steps(0, max_steps, evs);
         if (rc != FTGCR_OK) return rc;
@@ -522,8 +519,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
         // binary32 vectors inside, the correction accumulated into FP64 x
         L::init_state(tb, k, h->opt.ft, 1, max_steps, 0.0, 1, 1, s);
         while (true) {
-            L::residual(tb, h->nblk_st, h->kc, 1, s);
-            L::reduce_residual(tb, 1, 0, s);
+            L::residual(tb, h->nblk_st, h->kc, 1, 0, s);
             rc = run.read_state();
             if (rc != FTGCR_OK) return rc;
             const SolveState& hs = *h->st_host;
@@ -534,7 +530,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
             const long long cap = std::min<long long>(max_steps, hs.s + h->opt.inner_max_steps);
             const long long s0 = hs.s;
             L::init_state(tb, k, h->opt.ft, 1, cap, tau * tau, 0, 1, s);
-            L::reduce_residual(tb, 1, 1, s);
+            L::set_threshold(tb, 1, s);
             run.start_round();
             rc = run.run_steps(s0, cap, evs);
             if (rc != FTGCR_OK) return rc;
@@ -543,8 +539,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
         }
     }
     // FP64 true residual of the returned x
-    L::residual(tb, h->nblk_st, h->kc, 0, s);
-    L::reduce_residual(tb, 1, 0, s);
+    L::residual(tb, h->nblk_st, h->kc, 0, 0, s);
     HIP_TRY(h, hipEventRecord(h->ev_stop, s));
     rc = run.read_state();
     if (rc != FTGCR_OK) return rc;
@@ -716,7 +711,7 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
 ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, int32_t cap, int32_t* n_out)
 {
     if (!h || (!out && cap > 0)) return FTGCR_E_INVALID;
-    const int n = 6;
+    const int n = 3;
     for (int q = 0; q < n && q < cap; ++q) {
         std::memset(out[q].name, 0, sizeof out[q].name);
         std::strncpy(out[q].name, kKernelNames[q], sizeof out[q].name - 1);
@@ -730,7 +725,7 @@ ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, i
 ftgcr_status ftgcr_reset_kernel_times(ftgcr_handle* h)
 {
     if (!h) return FTGCR_E_INVALID;
-    for (int q = 0; q < 6; ++q) {
+    for (int q = 0; q < 3; ++q) {
         h->kt_ms[q] = 0.0;
         h->kt_n[q] = 0;
     }

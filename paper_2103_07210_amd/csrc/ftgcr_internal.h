@@ -129,15 +129,14 @@ struct Table {
 template <typename T> struct Launch {
     static void init_state(const Table<T>& tb, int k, int ft, int mixed, long long max_steps, double tol2,
                            int reset_counters, int grid, hipStream_t s);
-    static void residual(const Table<T>& tb, int total_st_blocks, int kc, int store, hipStream_t s);
-    static void reduce_residual(const Table<T>& tb, int n, int set_T, hipStream_t s);
+    static void set_threshold(const Table<T>& tb, int n, hipStream_t s);
+    static void residual(const Table<T>& tb, int total_st_blocks, int kc, int store, int set_T, hipStream_t s);
     static void update_thomas(const Table<T>& tb, int total_col_blocks, int H, int mode, hipStream_t s);
-    static void reduce_init(const Table<T>& tb, int n, hipStream_t s);
-    static void reduce_decide(const Table<T>& tb, int n, hipStream_t s);
+    static void finish_col(const Table<T>& tb, int mode, hipStream_t s);
     static void stencil_dots(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
-    static void reduce_alpha(const Table<T>& tb, int n, hipStream_t s);
+    static void finish_alpha(const Table<T>& tb, hipStream_t s);
+    static void finish_beta(const Table<T>& tb, int init, hipStream_t s);
     static void dir_update(const Table<T>& tb, int total_st_blocks, int kc, int init, hipStream_t s);
-    static void reduce_beta(const Table<T>& tb, int n, int init, hipStream_t s);
     static void finalize_x(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
     // fault events (single instance)
     static void event_prep(const Table<T>& tb, int vec, hipStream_t s);
@@ -145,7 +144,6 @@ template <typename T> struct Launch {
     static void event_inject(const Table<T>& tb, int grid, const long long* idx, const unsigned char* bits,
                              long long count, long long start, int bit, hipStream_t s);
     static void beta_dots(const Table<T>& tb, int total_st_blocks, hipStream_t s);
-    static void reduce_beta_dots(const Table<T>& tb, int n, hipStream_t s);
     // parity entry points (FP64 only)
     static void debug_apply_A(const Table<T>& tb, int total_st_blocks, int kc, const double* in, double* out, hipStream_t s);
     static void debug_pinv(const Table<T>& tb, int total_col_blocks, int H, const double* in, double* out, hipStream_t s);

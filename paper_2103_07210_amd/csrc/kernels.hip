@@ -1,21 +1,26 @@
 // FT-GCR device kernels for gfx950 (MI355X).
 //
-// One inner step of Algorithm 1 (FT-GCR(k), arXiv 2103.07210) runs as six
-// launches, each a streaming pass over HBM or a one-block decision:
+// One inner step of Algorithm 1 (FT-GCR(k), arXiv 2103.07210) runs as three
+// streaming passes over HBM, each followed by a one-block reduction:
 //
 //   update_thomas   r+ = r + beta L(p^nu), <r+, r+> partials, e = P^{-1} r+
-//   reduce_decide   exit test, monotone-norm fault test, backup or rollback
+//     finish_col    exit test, monotone-norm fault test, backup or rollback
+//                   (Algorithm 1, red part)
 //   stencil_dots    L(e) and the partials of <L(e), L(p^l)>, l = 0..nu
-//   reduce_alpha    alpha_l = -<L(e), L(p^l)> / <L(p^l), L(p^l)>
+//     finish_alpha  alpha_l = -<L(e), L(p^l)> / <L(p^l), L(p^l)>
 //   dir_update      p^{nu+1}, L(p^{nu+1}) (L(e) recomputed), the next beta's
 //                   inner products, and at the end of a cycle the deferred
 //                   iterate update phi += sum_l beta_l p^l
-//   reduce_beta     beta numerator / denominator, pass and cycle bookkeeping
+//     finish_beta   beta, pass and cycle bookkeeping
 //
-// Every reduction is deterministic: fixed per-block partition and order,
-// butterfly wave sums (bitwise equal on every lane), fixed cross-wave order,
-// then a fixed-order sum over block partials.  The detector's <r, r> is
-// therefore a function of r alone, as the equality case of the test needs.
+// The reductions are separate launches on purpose: a grid-wide "last block
+// finishes" scheme needs a device-scope fence and a same-address atomic per
+// block, which across the eight XCDs (eight L2s) of MI355X costs far more
+// than a launch.  Every reduction is deterministic: fixed per-block partition
+// and order, butterfly wave sums (bitwise equal on every lane), fixed
+// cross-wave order, then a fixed-order sum over the block partials.  The
+// detector's <r, r> is therefore a function of r alone, as the equality case
+// of the test needs.
 //
 // Storage type T is double (FP64 solve) or float (mixed precision: binary32
 // vectors, FP64 arithmetic in registers, FP64 inner products and iterate).
@@ -95,19 +100,27 @@ struct LevW {
     double w, e, s, n, b, a, diag;
 };
 
-__device__ __forceinline__ LevW level_weights(const ColW& c, const Geo& g, int k)
+// gc / gf: the vertical decay at centres and faces (global memory, or a
+// copy in LDS where per-level global loads would wait behind stores).
+__device__ __forceinline__ LevW level_weights(const ColW& c, const double* gc, const double* gf, int nz,
+                                              double opsig, int k)
 {
     LevW L;
-    const double gk = g.gc[k];
+    const double gk = gc[k];
     L.w = c.gx * (1.0 + c.hw * gk);
     L.e = c.gx * (1.0 + c.he * gk);
     L.s = c.gys * (1.0 + c.hs * gk);
     L.n = c.gyn * (1.0 + c.hn * gk);
-    L.b = (k > 0) ? c.gz * (1.0 + c.hc * g.gf[k]) : 0.0;
-    L.a = (k < g.nz - 1) ? c.gz * (1.0 + c.hc * g.gf[k + 1]) : 0.0;
+    L.b = (k > 0) ? c.gz * (1.0 + c.hc * gf[k]) : 0.0;
+    L.a = (k < nz - 1) ? c.gz * (1.0 + c.hc * gf[k + 1]) : 0.0;
     const double d0 = ((((L.w + L.e) + L.s) + L.n) + L.b) + L.a;
-    L.diag = g.opsig * d0;
+    L.diag = opsig * d0;
     return L;
+}
+
+__device__ __forceinline__ LevW level_weights(const ColW& c, const Geo& g, int k)
+{
+    return level_weights(c, g.gc, g.gf, g.nz, g.opsig, k);
 }
 
 __device__ __forceinline__ double apply_row(const LevW& L, double xc, double xw, double xe,
@@ -253,8 +266,19 @@ __global__ void k_init_state(Table<T> tb, int k, int ft, int mixed, long long ma
     st->ev_ok = 0;
 }
 
+// Exit threshold of the current round: tol^2 <R,R> (FP64 solve) or
+// tau^2 <r_t, r_t> (inner round of the mixed-precision refinement).
+template <typename T>
+__global__ void k_set_threshold(Table<T> tb)
+{
+    const int m = blockIdx.x;
+    if (m >= tb.n || threadIdx.x != 0) return;
+    SolveState* st = tb.inst[m].st;
+    st->T = st->tol2 * (st->mixed ? st->rt2 : st->RR);
+}
+
 // r = A x - R (x = caller's FP64 iterate), stored in R[r_dst] when `store`;
-// partials: <R, R> and <r, r> of the unrounded FP64 residual.
+// partials of <R, R> and of the unrounded FP64 <r, r>.
 template <typename T, int KC>
 __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
 {
@@ -262,22 +286,24 @@ __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
+    SolveState* st = in.st;
     const StPos ps = st_pos(in, lb);
+    T* rout = in.R[st->r_dst];
+    (void)st;
     double rr = 0.0, bb = 0.0;
     if (ps.valid) {
-        double ax[KC];
+        double ax[KC], b[KC];
         stencil_chunk<double, KC>(in.g, in.X[0], ps.i, ps.j, ps.k0, ax);
-        T* rout = in.R[in.st->r_dst];
+        const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + (long long)in.g.ncols * ps.k0;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) b[kk] = (ps.k0 + kk < in.g.nz) ? in.rhs[c0 + (long long)in.g.ncols * kk] : 0.0;
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
-            const int k = ps.k0 + kk;
-            if (k < in.g.nz) {
-                const long long c = (long long)ps.i + (long long)in.g.nx * ps.j + (long long)in.g.ncols * k;
-                const double b = in.rhs[c];
-                const double r = ax[kk] - b;
-                if (store) rout[c] = (T)r;
+            if (ps.k0 + kk < in.g.nz) {
+                const double r = ax[kk] - b[kk];
+                if (store) rout[c0 + (long long)in.g.ncols * kk] = (T)r;
                 rr = fma(r, r, rr);
-                bb = fma(b, b, bb);
+                bb = fma(b[kk], b[kk], bb);
             }
         }
     }
@@ -290,14 +316,14 @@ __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
 }
 
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_residual(Table<T> tb, int set_T)
+__global__ __launch_bounds__(RED_THREADS) void k_finish_residual(Table<T> tb, int set_T)
 {
     __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
+    SolveState* st = in.st;
     const double RR = sum_partials(in.part, in.nblk_st, 0, sh);
     const double rt2 = sum_partials(in.part, in.nblk_st, 1, sh);
     if (threadIdx.x == 0) {
-        SolveState* st = in.st;
         st->RR = RR;
         st->rt2 = rt2;
         if (set_T) st->T = st->tol2 * (st->mixed ? rt2 : RR);
@@ -305,180 +331,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_residual(Table<T> tb, in
 }
 
 // ---------------------------------------------------------------------------
-// update + column preconditioner
-// ---------------------------------------------------------------------------
-//
-// Each column (i, j) is split between two lanes of a wave (lane l and l+32):
-// the lower lane eliminates levels 0 .. h-1 upward (Thomas forward sweep),
-// the upper lane levels nz-1 .. h downward; they meet at row h-1, exchange
-// one pivot pair by a lane shuffle, and each back-substitutes its half.  The
-// elimination state of a half column (at most H levels) stays in registers.
-// P's rows: a_k e_{k-1} + b_k e_k + u_k e_{k+1} = r_k with b the diagonal of
-// A and a, u minus the vertical face weights.
-
-template <typename T, int H>
-__global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, int mode, const T* dbg_in,
-                                                               T* dbg_out)
-{
-    __shared__ double sh[4];
-    const int m = find_inst(tb.blk0_col, tb.n, blockIdx.x);
-    const Inst<T>& in = tb.inst[m];
-    const int lb = blockIdx.x - tb.blk0_col[m];
-    SolveState* st = in.st;
-    if (mode != MODE_DEBUG) {
-        if (st->status != RUNNING) return;
-        if (mode == MODE_STEP && st->d_cur == 0.0) return;
-    }
-    const Geo& g = in.g;
-    const int lane = threadIdx.x & 63;
-    const bool upper = lane >= 32;
-    const int col = lb * COLS_PER_BLOCK + (threadIdx.x >> 6) * 32 + (lane & 31);
-    const bool valid = col < g.ncols;
-    const int j = valid ? col / g.nx : 0;
-    const int i = valid ? col - j * g.nx : 0;
-    const long long plane = (long long)g.ncols;
-    const int nz = g.nz;
-    const int h = (nz + 1) >> 1;   // lower half: levels [0, h)
-    const int nup = nz - h;        // upper half: levels [h, nz)
-    const ColW c = col_weights(g, i, j);
-
-    const T* rin;
-    const T* ap = nullptr;
-    T* rout = nullptr;
-    T* eout;
-    double beta = 0.0;
-    if (mode == MODE_DEBUG) {
-        rin = dbg_in;
-        eout = dbg_out;
-    } else {
-        rin = in.R[st->r_cur];
-        eout = in.E;
-        if (mode == MODE_STEP) {
-            ap = in.AP[st->slot[st->nu]];
-            rout = in.R[st->r_dst];
-            beta = -st->beta_num / st->d_cur;
-        }
-    }
-
-    double acc_new = 0.0, acc_st = 0.0;
-    double ga[H], de[H];
-    double carry_g = 0.0, carry_d = 0.0;   // pivot pair carried along the sweep
-    double mm = 1.0, ff = 0.0, uu = 0.0;   // meeting row (lower lane)
-    const int nmine = upper ? nup : h;
-
-#pragma unroll
-    for (int q = 0; q < H; ++q) {
-        if (q < nmine) {
-            const int k = upper ? nz - 1 - q : q;
-            const long long o = (long long)col + plane * k;
-            double rp = 0.0;
-            if (valid) {
-                if (mode == MODE_STEP) {
-                    const double v = fma(beta, (double)ap[o], (double)rin[o]);
-                    const T sv = (T)v;
-                    rout[o] = sv;
-                    rp = (double)sv;
-                    acc_new = fma(v, v, acc_new);
-                    acc_st = fma(rp, rp, acc_st);
-                } else {
-                    rp = (double)rin[o];
-                    acc_new = fma(rp, rp, acc_new);
-                    acc_st = fma(rp, rp, acc_st);
-                }
-            }
-            const LevW L = level_weights(c, g, k);
-            const double a = -L.b, u = -L.a, b = L.diag;
-            if (!upper) {
-                const double mk = (q == 0) ? b : b - a * carry_g;
-                const double fk = (q == 0) ? rp : rp - a * carry_d;
-                if (q < h - 1) {
-                    const double inv = 1.0 / mk;
-                    carry_g = u * inv;
-                    carry_d = fk * inv;
-                    ga[q] = carry_g;
-                    de[q] = carry_d;
-                } else {
-                    mm = mk;
-                    ff = fk;
-                    uu = u;
-                }
-            } else {
-                const double den = (q == 0) ? b : b - u * carry_g;
-                const double fk = (q == 0) ? rp : rp - u * carry_d;
-                const double inv = 1.0 / den;
-                carry_g = a * inv;
-                carry_d = fk * inv;
-                ga[q] = carry_g;
-                de[q] = carry_d;
-            }
-        }
-    }
-    // meeting row: lower lane gets (zeta_h, eps_h) from its upper partner
-    const double zx = __shfl_xor(carry_g, 32);
-    const double ex = __shfl_xor(carry_d, 32);
-    double xm = 0.0;
-    if (!upper) xm = (ff - uu * ex) / (mm - uu * zx);
-    const double xl = __shfl_xor(xm, 32);
-    if (valid) {
-        if (!upper) {
-            eout[(long long)col + plane * (h - 1)] = (T)xm;
-            double xv = xm;
-#pragma unroll
-            for (int q = H - 1; q >= 0; --q) {
-                if (q <= h - 2) {
-                    xv = de[q] - ga[q] * xv;
-                    eout[(long long)col + plane * q] = (T)xv;
-                }
-            }
-        } else {
-            double xv = xl;
-#pragma unroll
-            for (int q = H - 1; q >= 0; --q) {
-                if (q < nup) {
-                    xv = de[q] - ga[q] * xv;
-                    eout[(long long)col + plane * (nz - 1 - q)] = (T)xv;
-                }
-            }
-        }
-    }
-    if (mode != MODE_DEBUG) {
-        const double sn = block_sum(acc_new, sh);
-        const double ss = block_sum(acc_st, sh);
-        if (threadIdx.x == 0) {
-            in.part[(long long)lb * NV_MAX + 0] = sn;
-            in.part[(long long)lb * NV_MAX + 1] = ss;
-        }
-    }
-}
-
-// After the initial residual and P^{-1} r^0: <r^0, r^0>, the exit test, and
-// the initial known-good state.
-template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_init(Table<T> tb)
-{
-    __shared__ double sh[4];
-    const Inst<T>& in = tb.inst[blockIdx.x];
-    SolveState* st = in.st;
-    if (st->status != RUNNING) return;
-    const double rn = sum_partials(in.part, in.nblk_col, 0, sh);
-    const double rs = sum_partials(in.part, in.nblk_col, 1, sh);
-    if (threadIdx.x == 0) {
-        st->rr_new = rn;
-        st->rr_old = rs;
-        if (rs <= st->T) {
-            st->status = FTGCR_CONVERGED;
-            st->x_final_hi = -1;
-        }
-        st->b_rr = rs;
-        st->b_accepted = st->accepted;
-        st->b_slot0 = st->slot[0];
-        st->r_bak = st->r_cur;
-        st->x_bak = st->x_base;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// decision of one step (Algorithm 1, exit test and red part)
+// decisions (single thread of the last block)
 // ---------------------------------------------------------------------------
 
 __device__ void rollback(SolveState* st)
@@ -497,16 +350,29 @@ __device__ void rollback(SolveState* st)
     st->nu = 0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_decide(Table<T> tb)
+// After the initial residual and P^{-1} r^0: <r^0, r^0>, the exit test, and
+// the initial known-good state.
+__device__ void decide_init(SolveState* st, double rn, double rs)
 {
-    __shared__ double sh[4];
-    const Inst<T>& in = tb.inst[blockIdx.x];
-    SolveState* st = in.st;
-    if (st->status != RUNNING) return;
-    const double rn = sum_partials(in.part, in.nblk_col, 0, sh);
-    const double rs = sum_partials(in.part, in.nblk_col, 1, sh);
-    if (threadIdx.x != 0) return;
+    st->rr_new = rn;
+    st->rr_old = rs;
+    if (rs <= st->T) {
+        st->status = FTGCR_CONVERGED;
+        st->x_final_hi = -1;
+    }
+    st->b_rr = rs;
+    st->b_accepted = st->accepted;
+    st->b_slot0 = st->slot[0];
+    st->r_bak = st->r_cur;
+    st->x_bak = st->x_base;
+}
+
+// One step's decision: exit test first, then the monotone residual-norm
+// fault test with rollback to the backup, else (first pass of a cycle) the
+// new backup.  rn: <r+, r+> of the unrounded update (detector), rs: of the
+// stored r+ (exit test and next reference); equal in FP64.
+__device__ void decide_step(SolveState* st, double rn, double rs, double* hist, long long hist_cap)
+{
     const int nu = st->nu;
     st->s += 1;
     const long long s = st->s;
@@ -517,10 +383,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_decide(Table<T> tb)
         return;
     }
     if (nu == 0) st->cycles += 1;
-    if (s <= in.hist_cap) in.hist[s - 1] = rn;
+    if (s <= hist_cap) hist[s - 1] = rn;
     st->beta[nu] = -st->beta_num / st->d_cur;
     st->rr_new = rn;
-    if (rs <= st->T) {   // exit test first
+    if (rs <= st->T) {
         st->accepted += 1;
         st->rr_old = rs;
         st->r_cur = st->r_dst;
@@ -529,7 +395,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_decide(Table<T> tb)
         st->active = 0;
         return;
     }
-    if (st->ft && !(rn < st->rr_old)) {   // norm did not decrease (NaN included)
+    if (st->ft && !(rn < st->rr_old)) {   // the norm did not decrease (NaN included)
         const long long pos = st->accepted + 1;
         const int stag = (pos == st->last_rb_pos) && !st->events_since_rb;
         st->detections += 1;
@@ -574,39 +440,275 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_decide(Table<T> tb)
     }
 }
 
+// After the new direction: the next beta's inner products, then pass and
+// cycle bookkeeping (p^k opens the next cycle).
+__device__ void decide_beta(SolveState* st, double num, double dn, int init)
+{
+    st->beta_num = num;
+    st->d_cur = dn;
+    if (init) {
+        st->d[0] = dn;
+        st->b_beta_num = num;
+        st->b_d0 = dn;
+        st->r_dst = other_r(st->r_cur, st->r_bak);
+        return;
+    }
+    const int nu = st->nu;
+    if (nu + 1 == st->k) {
+        st->x_base = st->x_dst;
+        st->x_base_nu = 0;
+        st->slot[0] = st->slot[st->k];
+        assign_slots(st, st->k);
+        st->nu = 0;
+        st->d[0] = dn;
+        st->r_dst = other_r(st->r_cur, st->r_bak);
+    } else {
+        st->nu = nu + 1;
+        st->d[nu + 1] = dn;
+        st->r_dst = st->r_cur;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// L(e) and orthogonalisation inner products
+// update + column preconditioner (+ the step's decision)
+// ---------------------------------------------------------------------------
+//
+// Each column (i, j) is split between two lanes of a wave (lane l and l+32):
+// the lower lane eliminates levels 0 .. h-1 upward (Thomas forward sweep),
+// the upper lane levels nz-1 .. h downward; they meet at row h-1, exchange
+// one pivot pair by a lane shuffle, and each back-substitutes its half.  The
+// elimination state of a half column (at most H levels) stays in registers.
+// P's rows: a_k e_{k-1} + b_k e_k + u_k e_{k+1} = r_k with b the diagonal of
+// A and a, u minus the vertical face weights.  All loads of a half column are
+// issued before its first store (r is updated in place after the first pass
+// of a cycle, so program order must not interleave them).
+
+template <typename T, int H, int mode>
+__global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, const T* dbg_in, T* dbg_out)
+{
+    __shared__ double sh[4];
+    __shared__ double s_gc[2 * H];
+    __shared__ double s_gf[2 * H + 1];
+    const int m = find_inst(tb.blk0_col, tb.n, blockIdx.x);
+    const Inst<T>& in = tb.inst[m];
+    const int lb = blockIdx.x - tb.blk0_col[m];
+    SolveState* st = in.st;
+    if (mode != MODE_DEBUG) {
+        if (st->status != RUNNING) return;
+        if (mode == MODE_STEP && st->d_cur == 0.0) return;   // finish_col records the breakdown
+    }
+    // everything read from the instance and the state is copied to registers
+    // before the first store, so no later access can wait behind a store
+    const Geo& g = in.g;
+    const int nx = g.nx, nz = g.nz, ncols = g.ncols;
+    const double opsig = g.opsig;
+    // vertical decay tables in LDS (LDS reads do not queue behind stores)
+    for (int t = threadIdx.x; t < nz; t += blockDim.x) s_gc[t] = g.gc[t];
+    for (int t = threadIdx.x; t <= nz; t += blockDim.x) s_gf[t] = g.gf[t];
+    const T* rin;
+    const T* ap;
+    T* rout;
+    T* eout;
+    double beta = 0.0;
+    if (mode == MODE_DEBUG) {
+        rin = dbg_in;
+        ap = dbg_in;
+        rout = nullptr;
+        eout = dbg_out;
+    } else {
+        rin = in.R[st->r_cur];
+        eout = in.E;
+        ap = rin;
+        rout = nullptr;
+        if (mode == MODE_STEP) {
+            ap = in.AP[st->slot[st->nu]];
+            rout = in.R[st->r_dst];
+            beta = -st->beta_num / st->d_cur;
+        }
+    }
+    double* part = in.part;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const bool upper = lane >= 32;
+    const int col = lb * COLS_PER_BLOCK + (threadIdx.x >> 6) * 32 + (lane & 31);
+    const bool valid = col < ncols;
+    const int colc = valid ? col : 0;
+    const int j = colc / nx;
+    const int i = colc - j * nx;
+    const long long plane = (long long)ncols;
+    const int h = (nz + 1) >> 1;   // lower half: levels [0, h)
+    const int nup = nz - h;        // upper half: levels [h, nz)
+    const int nmine = upper ? nup : h;
+    const ColW c = col_weights(g, i, j);
+
+    // The half column streams in chunks of CH levels, each chunk's loads
+    // issued one chunk ahead of its elimination (a two-stage software
+    // pipeline): loads are branch-free (clamped addresses, results
+    // selected), so a chunk's loads are all in flight together, and they are
+    // issued before the previous chunk's stores, so waiting for them never
+    // waits for a store.  The elimination is the same instruction stream
+    // for both halves: the lower lane eliminates towards level 0 (near
+    // coupling a_k, far coupling u_k), the upper lane towards nz-1 (near
+    // u_k, far a_k).
+    constexpr int CH = H < 8 ? H : 8;
+    constexpr int NCH = H / CH;
+    double bufr[2][CH], bufa[2][CH];
+    double de[H], ga[H];
+    double acc_new = 0.0, acc_st = 0.0;
+    double carry_g = 0.0, carry_d = 0.0;
+    double mm = 1.0, ff = 0.0, uu = 0.0;   // meeting row of the lower lane
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        int k = upper ? nz - 1 - t : t;
+        k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
+        const long long o = (long long)colc + plane * k;
+        bufr[0][t] = (double)rin[o];
+        bufa[0][t] = (mode == MODE_STEP) ? (double)ap[o] : 0.0;
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCH; ++cb) {
+        const int b = cb & 1;
+        if (cb + 1 < NCH) {
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                const int q = (cb + 1) * CH + t;
+                int k = upper ? nz - 1 - q : q;
+                k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
+                const long long o = (long long)colc + plane * k;
+                bufr[b ^ 1][t] = (double)rin[o];
+                bufa[b ^ 1][t] = (mode == MODE_STEP) ? (double)ap[o] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            const int q = cb * CH + t;
+            const bool mine = q < nmine;
+            int k = upper ? nz - 1 - q : q;
+            k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
+            const double v = (mode == MODE_STEP) ? fma(beta, bufa[b][t], bufr[b][t]) : bufr[b][t];
+            const T sv = (T)v;
+            const double rp = (double)sv;
+            if (mine && valid) {
+                if (mode == MODE_STEP) rout[(long long)colc + plane * k] = sv;
+                acc_new = fma(v, v, acc_new);
+                acc_st = fma(rp, rp, acc_st);
+            }
+            const LevW L = level_weights(c, s_gc, s_gf, nz, opsig, k);
+            const double near = upper ? -L.a : -L.b;
+            const double far = upper ? -L.b : -L.a;
+            const double mk = (q == 0) ? L.diag : L.diag - near * carry_g;
+            const double fk = (q == 0) ? rp : rp - near * carry_d;
+            const bool meet = !upper && q == h - 1;
+            if (meet) {
+                mm = mk;
+                ff = fk;
+                uu = far;
+            }
+            const double inv = 1.0 / mk;
+            const double g_new = far * inv;
+            const double d_new = fk * inv;
+            if (mine) {
+                carry_g = meet ? carry_g : g_new;
+                carry_d = meet ? carry_d : d_new;
+            }
+            ga[q] = g_new;
+            de[q] = d_new;
+        }
+    }
+    // meeting row: the lower lane gets (zeta_h, eps_h) from its upper partner
+    const double zx = __shfl_xor(carry_g, 32);
+    const double ex = __shfl_xor(carry_d, 32);
+    const double xm = (ff - uu * ex) / (mm - uu * zx);
+    const double xl = __shfl_xor(xm, 32);
+    // back-substitution: lower lane from level h-2 down to 0 (after storing
+    // the meeting value at h-1), upper lane from level h up to nz-1
+    double xv = upper ? xl : xm;
+    if (valid && !upper) eout[(long long)colc + plane * (h - 1)] = (T)xm;
+    const int nback = upper ? nup : h - 1;
+#pragma unroll
+    for (int q = H - 1; q >= 0; --q) {
+        if (q < nback) {
+            xv = de[q] - ga[q] * xv;
+            const int k = upper ? nz - 1 - q : q;
+            if (valid) eout[(long long)colc + plane * k] = (T)xv;
+        }
+    }
+    if (mode == MODE_DEBUG) return;
+    const double sn = block_sum(acc_new, sh);
+    const double ss = block_sum(acc_st, sh);
+    if (threadIdx.x == 0) {
+        part[(long long)lb * NV_MAX + 0] = sn;
+        part[(long long)lb * NV_MAX + 1] = ss;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mode)
+{
+    __shared__ double sh[4];
+    const Inst<T>& in = tb.inst[blockIdx.x];
+    SolveState* st = in.st;
+    if (st->status != RUNNING) return;
+    const double rn = sum_partials(in.part, in.nblk_col, 0, sh);
+    const double rs = sum_partials(in.part, in.nblk_col, 1, sh);
+    if (threadIdx.x == 0) {
+        if (mode == MODE_STEP) decide_step(st, rn, rs, in.hist, in.hist_cap);
+        else decide_init(st, rn, rs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// L(e) and orthogonalisation inner products (+ alpha)
 // ---------------------------------------------------------------------------
 
 template <typename T, int KC>
 __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
 {
-    __shared__ double sh[4];
+    __shared__ double sh[KMAX + 1][4];
+    __shared__ const T* s_ap[KMAX + 1];
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
-    const SolveState* st = in.st;
+    SolveState* st = in.st;
     if (st->status != RUNNING || !st->active) return;
     const int nu = st->nu;
+    if ((int)threadIdx.x <= nu) s_ap[threadIdx.x] = in.AP[st->slot[threadIdx.x]];
+    __syncthreads();
     const StPos ps = st_pos(in, lb);
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + plane * ps.k0;
     double le[KC];
     if (ps.valid) stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, le);
-    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + (long long)in.g.ncols * ps.k0;
-    for (int l = 0; l <= nu; ++l) {
-        const T* apl = in.AP[st->slot[l]];
-        double acc = 0.0;
-        if (ps.valid) {
+    // every <L(e), L(p^l)> at once: all loads visible to the scheduler
+    double acc[KMAX + 1];
+#pragma unroll
+    for (int l = 0; l <= KMAX; ++l) {
+        acc[l] = 0.0;
+        if (l <= nu && ps.valid) {
+            const T* apl = s_ap[l];
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk)
-                if (ps.k0 + kk < in.g.nz) acc = fma(le[kk], (double)apl[c0 + (long long)in.g.ncols * kk], acc);
+                if (ps.k0 + kk < in.g.nz) acc[l] = fma(le[kk], (double)apl[c0 + plane * kk], acc[l]);
         }
-        const double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) in.part[(long long)lb * NV_MAX + l] = s;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int l = 0; l <= KMAX; ++l) {
+        if (l <= nu) {
+            const double v = wave_sum(acc[l]);
+            if (lane == 0) sh[l][w] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= nu) {
+        const int l = threadIdx.x;
+        in.part[(long long)lb * NV_MAX + l] = ((sh[l][0] + sh[l][1]) + sh[l][2]) + sh[l][3];
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_alpha(Table<T> tb)
+__global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(Table<T> tb)
 {
     __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
@@ -628,48 +730,78 @@ template <typename T, int KC>
 __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init)
 {
     __shared__ double sh[4];
+    __shared__ const T* s_p[KMAX + 1];
+    __shared__ const T* s_ap[KMAX + 1];
+    __shared__ double s_al[KMAX + 1];
+    __shared__ double s_be[KMAX + 1];
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
-    const SolveState* st = in.st;
+    SolveState* st = in.st;
     if (st->status != RUNNING) return;
     if (!init && !st->active) return;
     const int nu = init ? -1 : st->nu;
     const int target = st->slot[nu + 1];
     const bool xupd = !init && (nu == st->k - 1);
     const int xlo = st->x_base_nu;
+    T* pout = in.P[target];
+    T* apout = in.AP[target];
+    const T* rv = in.R[st->r_cur];
+    const double* xb = in.X[st->x_base];
+    double* xo = in.X[st->x_dst];
+    if ((int)threadIdx.x <= nu) {
+        const int sl = st->slot[threadIdx.x];
+        s_p[threadIdx.x] = in.P[sl];
+        s_ap[threadIdx.x] = in.AP[sl];
+        s_al[threadIdx.x] = st->alpha[threadIdx.x];
+        s_be[threadIdx.x] = (xupd && (int)threadIdx.x >= xlo) ? st->beta[threadIdx.x] : 0.0;
+    }
+    __syncthreads();
     const StPos ps = st_pos(in, lb);
-    double le[KC];
-    if (ps.valid) stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, le);
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + plane * ps.k0;
     double acc_num = 0.0, acc_d = 0.0;
     if (ps.valid) {
-        T* pout = in.P[target];
-        T* apout = in.AP[target];
-        const T* r = in.R[st->r_cur];
-        const double* xb = in.X[st->x_base];
-        double* xo = in.X[st->x_dst];
+        double a[KC], p[KC], xa[KC], r[KC];
+        stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a);
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const bool ok = ps.k0 + kk < in.g.nz;
+            const long long c = c0 + plane * kk;
+            p[kk] = ok ? (double)in.E[c] : 0.0;
+            r[kk] = ok ? (double)rv[c] : 0.0;
+            xa[kk] = (ok && xupd) ? xb[c] : 0.0;
+        }
+#pragma unroll
+        for (int l = 0; l < KMAX; ++l) {
+            if (l <= nu) {
+                const T* pl = s_p[l];
+                const T* apl = s_ap[l];
+                const double al = s_al[l];
+                const double bl = s_be[l];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    if (ps.k0 + kk < in.g.nz) {
+                        const long long c = c0 + plane * kk;
+                        const double pv = (double)pl[c];
+                        p[kk] = fma(al, pv, p[kk]);
+                        a[kk] = fma(al, (double)apl[c], a[kk]);
+                        if (xupd) xa[kk] = fma(bl, pv, xa[kk]);
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             if (ps.k0 + kk < in.g.nz) {
-                const long long c = (long long)ps.i + (long long)in.g.nx * ps.j + (long long)in.g.ncols * (ps.k0 + kk);
-                double p = (double)in.E[c];
-                double a = le[kk];
-                double xa = xupd ? xb[c] : 0.0;
-                for (int l = 0; l <= nu; ++l) {
-                    const int sl = st->slot[l];
-                    const double pl = (double)in.P[sl][c];
-                    const double al = st->alpha[l];
-                    p = fma(al, pl, p);
-                    a = fma(al, (double)in.AP[sl][c], a);
-                    if (xupd && l >= xlo) xa = fma(st->beta[l], pl, xa);
-                }
-                const T ps_ = (T)p;
-                const T as_ = (T)a;
+                const long long c = c0 + plane * kk;
+                const T ps_ = (T)p[kk];
+                const T as_ = (T)a[kk];
                 pout[c] = ps_;
                 apout[c] = as_;
-                if (xupd) xo[c] = xa;
+                if (xupd) xo[c] = xa[kk];
                 const double ad = (double)as_;
-                acc_num = fma((double)r[c], ad, acc_num);
+                acc_num = fma(r[kk], ad, acc_num);
                 acc_d = fma(ad, ad, acc_d);
             }
         }
@@ -683,7 +815,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
 }
 
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_beta(Table<T> tb, int init)
+__global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int init)
 {
     __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
@@ -692,30 +824,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_beta(Table<T> tb, int in
     if (!init && !st->active) return;
     const double num = sum_partials(in.part, in.nblk_st, 0, sh);
     const double dn = sum_partials(in.part, in.nblk_st, 1, sh);
-    if (threadIdx.x != 0) return;
-    st->beta_num = num;
-    st->d_cur = dn;
-    if (init) {
-        st->d[0] = dn;
-        st->b_beta_num = num;
-        st->b_d0 = dn;
-        st->r_dst = other_r(st->r_cur, st->r_bak);
-        return;
-    }
-    const int nu = st->nu;
-    if (nu + 1 == st->k) {   // end of the k passes: p^k opens the next cycle
-        st->x_base = st->x_dst;
-        st->x_base_nu = 0;
-        st->slot[0] = st->slot[st->k];
-        assign_slots(st, st->k);
-        st->nu = 0;
-        st->d[0] = dn;
-        st->r_dst = other_r(st->r_cur, st->r_bak);
-    } else {
-        st->nu = nu + 1;
-        st->d[nu + 1] = dn;
-        st->r_dst = st->r_cur;
-    }
+    if (threadIdx.x == 0) decide_beta(st, num, dn, init);
 }
 
 // x = x_base + sum_{l = x_base_nu .. x_final_hi} beta_l p^l, into X[0].
@@ -848,7 +957,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
 {
     __shared__ double sh[4];
     const Inst<T>& in = tb.inst[0];
-    const SolveState* st = in.st;
+    SolveState* st = in.st;
     if (!st->ev_ok) return;
     const int lb = blockIdx.x;
     const StPos ps = st_pos(in, lb);
@@ -874,7 +983,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
 }
 
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_beta_dots(Table<T> tb)
+__global__ __launch_bounds__(RED_THREADS) void k_finish_beta_dots(Table<T> tb)
 {
     __shared__ double sh[4];
     const Inst<T>& in = tb.inst[0];
@@ -911,23 +1020,23 @@ __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, 
 // launchers
 // ---------------------------------------------------------------------------
 
-#define FTGCR_KC_SWITCH(kc, CALL)            \
-    switch (kc) {                            \
-    case 1: { constexpr int KCV = 1; CALL; } break;   \
-    case 2: { constexpr int KCV = 2; CALL; } break;   \
-    case 4: { constexpr int KCV = 4; CALL; } break;   \
-    case 8: { constexpr int KCV = 8; CALL; } break;   \
-    default: { constexpr int KCV = 16; CALL; } break; \
+#define FTGCR_KC_SWITCH(kc, CALL)                         \
+    switch (kc) {                                         \
+    case 1: { constexpr int KCV = 1; CALL; } break;       \
+    case 2: { constexpr int KCV = 2; CALL; } break;       \
+    case 4: { constexpr int KCV = 4; CALL; } break;       \
+    case 8: { constexpr int KCV = 8; CALL; } break;       \
+    default: { constexpr int KCV = 16; CALL; } break;     \
     }
 
-#define FTGCR_H_SWITCH(H, CALL)                       \
-    switch (H) {                                      \
-    case 4: { constexpr int HV = 4; CALL; } break;    \
-    case 8: { constexpr int HV = 8; CALL; } break;    \
-    case 16: { constexpr int HV = 16; CALL; } break;  \
-    case 24: { constexpr int HV = 24; CALL; } break;  \
-    case 32: { constexpr int HV = 32; CALL; } break;  \
-    default: { constexpr int HV = 48; CALL; } break;  \
+#define FTGCR_H_SWITCH(H, CALL)                           \
+    switch (H) {                                          \
+    case 4: { constexpr int HV = 4; CALL; } break;        \
+    case 8: { constexpr int HV = 8; CALL; } break;        \
+    case 16: { constexpr int HV = 16; CALL; } break;      \
+    case 24: { constexpr int HV = 24; CALL; } break;      \
+    case 32: { constexpr int HV = 32; CALL; } break;      \
+    default: { constexpr int HV = 48; CALL; } break;      \
     }
 
 int thomas_depth(int nz)
@@ -948,34 +1057,45 @@ void Launch<T>::init_state(const Table<T>& tb, int k, int ft, int mixed, long lo
 }
 
 template <typename T>
-void Launch<T>::residual(const Table<T>& tb, int total, int kc, int store, hipStream_t s)
+void Launch<T>::set_threshold(const Table<T>& tb, int n, hipStream_t s)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_residual<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb, store));
+    hipLaunchKernelGGL(k_set_threshold<T>, dim3(n), dim3(64), 0, s, tb);
 }
 
 template <typename T>
-void Launch<T>::reduce_residual(const Table<T>& tb, int n, int set_T, hipStream_t s)
+void Launch<T>::residual(const Table<T>& tb, int total, int kc, int store, int set_T, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_residual<T>, dim3(n), dim3(RED_THREADS), 0, s, tb, set_T);
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_residual<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb, store));
+    hipLaunchKernelGGL(k_finish_residual<T>, dim3(tb.n), dim3(RED_THREADS), 0, s, tb, set_T);
 }
 
 template <typename T>
 void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hipStream_t s)
 {
-    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV>), dim3(total), dim3(COL_THREADS), 0, s, tb,
-                                         mode, (const T*)nullptr, (T*)nullptr));
+    if (mode == MODE_STEP)
+        FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV, MODE_STEP>), dim3(total), dim3(COL_THREADS), 0,
+                                             s, tb, (const T*)nullptr, (T*)nullptr))
+    else
+        FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV, MODE_INIT>), dim3(total), dim3(COL_THREADS), 0,
+                                             s, tb, (const T*)nullptr, (T*)nullptr))
 }
 
 template <typename T>
-void Launch<T>::reduce_init(const Table<T>& tb, int n, hipStream_t s)
+void Launch<T>::finish_col(const Table<T>& tb, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_init<T>, dim3(n), dim3(RED_THREADS), 0, s, tb);
+    hipLaunchKernelGGL(k_finish_col<T>, dim3(tb.n), dim3(RED_THREADS), 0, s, tb, mode);
 }
 
 template <typename T>
-void Launch<T>::reduce_decide(const Table<T>& tb, int n, hipStream_t s)
+void Launch<T>::finish_alpha(const Table<T>& tb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_decide<T>, dim3(n), dim3(RED_THREADS), 0, s, tb);
+    hipLaunchKernelGGL(k_finish_alpha<T>, dim3(tb.n), dim3(RED_THREADS), 0, s, tb);
+}
+
+template <typename T>
+void Launch<T>::finish_beta(const Table<T>& tb, int init, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish_beta<T>, dim3(tb.n), dim3(RED_THREADS), 0, s, tb, init);
 }
 
 template <typename T>
@@ -985,21 +1105,9 @@ void Launch<T>::stencil_dots(const Table<T>& tb, int total, int kc, hipStream_t 
 }
 
 template <typename T>
-void Launch<T>::reduce_alpha(const Table<T>& tb, int n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reduce_alpha<T>, dim3(n), dim3(RED_THREADS), 0, s, tb);
-}
-
-template <typename T>
 void Launch<T>::dir_update(const Table<T>& tb, int total, int kc, int init, hipStream_t s)
 {
     FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_dir_update<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb, init));
-}
-
-template <typename T>
-void Launch<T>::reduce_beta(const Table<T>& tb, int n, int init, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reduce_beta<T>, dim3(n), dim3(RED_THREADS), 0, s, tb, init);
 }
 
 template <typename T>
@@ -1031,12 +1139,7 @@ template <typename T>
 void Launch<T>::beta_dots(const Table<T>& tb, int total, hipStream_t s)
 {
     hipLaunchKernelGGL(k_beta_dots<T>, dim3(total), dim3(ST_THREADS), 0, s, tb);
-}
-
-template <typename T>
-void Launch<T>::reduce_beta_dots(const Table<T>& tb, int n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reduce_beta_dots<T>, dim3(n), dim3(RED_THREADS), 0, s, tb);
+    hipLaunchKernelGGL(k_finish_beta_dots<T>, dim3(1), dim3(RED_THREADS), 0, s, tb);
 }
 
 template <typename T>
@@ -1060,8 +1163,8 @@ template <>
 void Launch<double>::debug_pinv(const Table<double>& tb, int total, int H, const double* in, double* out,
                                 hipStream_t s)
 {
-    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV>), dim3(total), dim3(COL_THREADS), 0, s,
-                                         tb, (int)MODE_DEBUG, in, out));
+    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_DEBUG>), dim3(total), dim3(COL_THREADS),
+                                         0, s, tb, in, out));
 }
 
 template struct Launch<double>;
