@@ -59,6 +59,11 @@ struct ftgcr_handle {
     void* ws = nullptr;
     size_t ws_bytes = 0;
 
+    // captured step sequence: `graph_steps` steps replayed as one graph
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+
     int nblk_col = 0, nblk_st = 0;
     int kc = 1, tx = 1, ty = 1, tz = 1, H = 4;
 
@@ -103,13 +108,15 @@ double hill_height(const ftgcr_coeffs& c, double lon, double lat)
     return std::exp(-q * q);
 }
 
+// Levels per stencil block: as many as keep >= 1024 blocks in flight (8 at
+// most: deeper chunks raise register pressure more than they save halo).
 int auto_levels_per_block(int tx, int ty, int nz)
 {
     const long long cols = (long long)tx * ty;
-    const int cand[] = {16, 8, 4, 2};
+    const int cand[] = {8, 4, 2};
     for (int kc : cand) {
         const long long blocks = cols * ((nz + kc - 1) / kc);
-        if (blocks >= 2048 && kc <= nz) return kc;
+        if (blocks >= 1024 && kc <= nz) return kc;
     }
     return 1;
 }
@@ -160,6 +167,7 @@ Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x)
     in.X[0] = x;
     in.X[1] = (double*)p; p += L.xvec;
     in.part = (double*)p; p += L.part;
+    in.pstride = std::max(h->nblk_col, h->nblk_st);
     in.hist = (double*)p;
     in.hist_cap = h->opt.hist_cap;
     in.rhs = rhs;
@@ -313,6 +321,33 @@ struct Runner {
         h->pending.push_back({cls, cur_step, a, b});
     }
 
+    // Replay `n` steps as one captured graph (captured on first use; the
+    // graph holds kernel launches only and every argument is fixed for the
+    // handle: the per-solve data live in the device-side instance record).
+    ftgcr_status replay(int n)
+    {
+        if (!h->graph || h->graph_steps != n) {
+            if (h->graph) {
+                (void)hipGraphExecDestroy(h->graph);
+                h->graph = nullptr;
+            }
+            Runner cap{h, tb, h->cap_stream};
+            HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+            for (int q = 0; q < n; ++q) cap.step(0);
+            hipGraph_t g = nullptr;
+            HIP_TRY(h, hipStreamEndCapture(h->cap_stream, &g));
+            hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                h->graph = nullptr;
+                return fail(h, FTGCR_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            h->graph_steps = n;
+        }
+        HIP_TRY(h, hipGraphLaunch(h->graph, s));
+        return FTGCR_OK;
+    }
+
     void step(long long number)
     {
         cur_step = number;
@@ -384,7 +419,12 @@ struct Runner {
                 long long cnt = chunk;
                 if (evp < evs.size()) cnt = std::min<long long>(cnt, evs[evp].step - 1 - launched);
                 cnt = std::max<long long>(cnt, 1);
-                for (long long q = 0; q < cnt; ++q) step(launched + 1 + q);
+                if (cnt == chunk && h->opt.use_graphs && !h->opt.profile_kernels) {
+                    ftgcr_status rc = replay(chunk);
+                    if (rc != FTGCR_OK) return rc;
+                } else {
+                    for (long long q = 0; q < cnt; ++q) step(launched + 1 + q);
+                }
                 launched += cnt;
                 issued += cnt;
             }
@@ -636,6 +676,10 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
     }
     rc = upload_debug_inst(h);
     if (rc != FTGCR_OK) return bail(rc);
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        h->err = "hipStreamCreate failed";
+        return bail(FTGCR_E_HIP);
+    }
     *out = h;
     return FTGCR_OK;
 }
@@ -648,6 +692,11 @@ ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt)
         return fail(h, FTGCR_E_INVALID, "invalid options");
     h->opt = *opt;
     set_tiling(h);
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+        h->graph_steps = 0;
+    }
     return upload_debug_inst(h);
 }
 
@@ -736,6 +785,8 @@ void ftgcr_destroy(ftgcr_handle* h)
 {
     if (!h) return;
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->tables) (void)hipFree(h->tables);
     if (h->st) (void)hipFree(h->st);
     if (h->inst) (void)hipFree(h->inst);

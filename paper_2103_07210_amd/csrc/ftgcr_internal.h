@@ -106,7 +106,8 @@ struct Inst {
     double* X[2];            // X[0]: caller's x, X[1]: workspace
     const double* rhs;
     SolveState* st;
-    double* part;            // block partials [nblk][NV_MAX]
+    double* part;            // block partials [NV_MAX][pstride] (value-major)
+    long long pstride;       // >= blocks of either grid
     double* hist;
     long long hist_cap;
     int nblk_col;            // blocks of the column grid

@@ -63,11 +63,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-// Fixed-order sum of one value over an instance's block partials.
-__device__ __forceinline__ double sum_partials(const double* part, int nblk, int q, double* sh)
+// Fixed-order sum of value q over an instance's block partials (stored
+// value-major, so a value's partials are contiguous).
+template <typename T>
+__device__ __forceinline__ double sum_partials(const Inst<T>& in, int nblk, int q, double* sh)
 {
+    const double* part = in.part + (long long)q * in.pstride;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RED_THREADS) acc += part[(long long)b * NV_MAX + q];
+    for (int b = threadIdx.x; b < nblk; b += RED_THREADS) acc += part[b];
     return block_sum(acc, sh);
 }
 
@@ -135,43 +138,57 @@ __device__ __forceinline__ double apply_row(const LevW& L, double xc, double xw,
     return fma(L.diag, xc, -off);
 }
 
-// (A x) at levels k0 .. k0+KC-1 of column (i, j); missing neighbours
-// (beyond the poles, bottom, top) enter as 0 with weight 0.
+// (A x) at levels k0 .. k0+KC-1 of column (i, j) (i, j in range, k0 < nz).
+// Branch-free: every load uses a clamped in-range address and is issued up
+// front; missing neighbours (beyond the poles, bottom, top) are then
+// selected to 0 (a select, not a product, so a NaN at the clamped address
+// cannot leak) and carry weight 0.  Entries at levels >= nz are garbage and
+// must be masked by the caller.
 template <typename TI, int KC>
 __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict__ x, int i, int j,
                                               int k0, double (&out)[KC])
 {
     const ColW c = col_weights(g, i, j);
+    const int nz = g.nz;
     const long long plane = (long long)g.ncols;
     const int iw = (i == 0) ? g.nx - 1 : i - 1;
     const int ie = (i == g.nx - 1) ? 0 : i + 1;
+    const bool has_s = j > 0, has_n = j < g.ny - 1;
     const long long row = (long long)j * g.nx;
-    double xprev = (k0 > 0) ? (double)x[row + i + plane * (k0 - 1)] : 0.0;
-    double xcur = (double)x[row + i + plane * k0];
+    const long long so = has_s ? -(long long)g.nx : 0;
+    const long long no = has_n ? (long long)g.nx : 0;
+    double xv[KC + 2], xw[KC], xe[KC], xs[KC], xn[KC];
+#pragma unroll
+    for (int t = 0; t < KC + 2; ++t) {
+        int k = k0 - 1 + t;
+        k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
+        xv[t] = (double)x[row + i + plane * k];
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+        const long long o = row + plane * k;
+        xw[kk] = (double)x[o + iw];
+        xe[kk] = (double)x[o + ie];
+        xs[kk] = (double)x[o + i + so];
+        xn[kk] = (double)x[o + i + no];
+    }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
-        if (k < g.nz) {
-            const long long o = row + plane * k;
-            const double xnext = (k + 1 < g.nz) ? (double)x[o + plane + i] : 0.0;
-            const double xw = (double)x[o + iw];
-            const double xe = (double)x[o + ie];
-            const double xs = (j > 0) ? (double)x[o - g.nx + i] : 0.0;
-            const double xn = (j < g.ny - 1) ? (double)x[o + g.nx + i] : 0.0;
-            const LevW L = level_weights(c, g, k);
-            out[kk] = apply_row(L, xcur, xw, xe, xs, xn, xprev, xnext);
-            xprev = xcur;
-            xcur = xnext;
-        } else {
-            out[kk] = 0.0;
-        }
+        const int kq = (k > nz - 1) ? nz - 1 : k;
+        const LevW L = level_weights(c, g, kq);
+        const double xb = (k > 0) ? xv[kk] : 0.0;
+        const double xa = (k + 1 < nz) ? xv[kk + 2] : 0.0;
+        out[kk] = apply_row(L, xv[kk + 1], xw[kk], xe[kk], has_s ? xs[kk] : 0.0, has_n ? xn[kk] : 0.0, xb, xa);
     }
 }
 
-// Stencil-grid coordinates of this thread.
+// Stencil-grid coordinates of this thread: (i, j) clamped into the grid for
+// addressing, `col_ok` whether the thread owns a real column.
 struct StPos {
     int i, j, k0;
-    bool valid;
+    bool col_ok;
 };
 
 template <typename T>
@@ -182,10 +199,12 @@ __device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb)
     const int t = lb / in.tx;
     const int by = t % in.ty;
     const int bz = t / in.ty;
-    p.i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
-    p.j = by * ST_TY + (threadIdx.x / ST_TX);
+    const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
+    const int j = by * ST_TY + (threadIdx.x / ST_TX);
+    p.col_ok = i < in.g.nx && j < in.g.ny;
+    p.i = i < in.g.nx ? i : in.g.nx - 1;
+    p.j = j < in.g.ny ? j : in.g.ny - 1;
     p.k0 = bz * in.kc;
-    p.valid = p.i < in.g.nx && p.j < in.g.ny && p.k0 < in.g.nz;
     return p;
 }
 
@@ -286,32 +305,34 @@ __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
-    SolveState* st = in.st;
     const StPos ps = st_pos(in, lb);
-    T* rout = in.R[st->r_dst];
-    (void)st;
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    T* rout = in.R[in.st->r_dst];
+    const double* rhs = in.rhs;
+    double ax[KC], b[KC];
+    stencil_chunk<double, KC>(in.g, in.X[0], ps.i, ps.j, ps.k0, ax);
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        b[kk] = rhs[c0 + plane * kq];
+    }
     double rr = 0.0, bb = 0.0;
-    if (ps.valid) {
-        double ax[KC], b[KC];
-        stencil_chunk<double, KC>(in.g, in.X[0], ps.i, ps.j, ps.k0, ax);
-        const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + (long long)in.g.ncols * ps.k0;
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) b[kk] = (ps.k0 + kk < in.g.nz) ? in.rhs[c0 + (long long)in.g.ncols * kk] : 0.0;
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            if (ps.k0 + kk < in.g.nz) {
-                const double r = ax[kk] - b[kk];
-                if (store) rout[c0 + (long long)in.g.ncols * kk] = (T)r;
-                rr = fma(r, r, rr);
-                bb = fma(b[kk], b[kk], bb);
-            }
-        }
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        const double r = ok ? ax[kk] - b[kk] : 0.0;
+        const double bv = ok ? b[kk] : 0.0;
+        if (ok && store) rout[c0 + plane * (ps.k0 + kk)] = (T)r;
+        rr = fma(r, r, rr);
+        bb = fma(bv, bv, bb);
     }
     const double sb = block_sum(bb, sh);
     const double sr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        in.part[(long long)lb * NV_MAX + 0] = sb;
-        in.part[(long long)lb * NV_MAX + 1] = sr;
+        in.part[(long long)(0) * in.pstride + lb] = sb;
+        in.part[(long long)(1) * in.pstride + lb] = sr;
     }
 }
 
@@ -321,8 +342,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_residual(Table<T> tb, in
     __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
-    const double RR = sum_partials(in.part, in.nblk_st, 0, sh);
-    const double rt2 = sum_partials(in.part, in.nblk_st, 1, sh);
+    const double RR = sum_partials(in, in.nblk_st, 0, sh);
+    const double rt2 = sum_partials(in, in.nblk_st, 1, sh);
     if (threadIdx.x == 0) {
         st->RR = RR;
         st->rt2 = rt2;
@@ -527,6 +548,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
         }
     }
     double* part = in.part;
+    const long long pstride = in.pstride;
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -541,6 +563,11 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const int nup = nz - h;        // upper half: levels [h, nz)
     const int nmine = upper ? nup : h;
     const ColW c = col_weights(g, i, j);
+    // horizontal part of the diagonal: sum of the four side weights is
+    // h0 + g_k h1 with per-column constants (fewer operations per level than
+    // forming the four weights; equal up to rounding)
+    const double h0 = ((c.gx + c.gx) + c.gys) + c.gyn;
+    const double h1 = (c.gx * (c.hw + c.he) + c.gys * c.hs) + c.gyn * c.hn;
 
     // The half column streams in chunks of CH levels, each chunk's loads
     // issued one chunk ahead of its elimination (a two-stage software
@@ -594,10 +621,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
                 acc_new = fma(v, v, acc_new);
                 acc_st = fma(rp, rp, acc_st);
             }
-            const LevW L = level_weights(c, s_gc, s_gf, nz, opsig, k);
-            const double near = upper ? -L.a : -L.b;
-            const double far = upper ? -L.b : -L.a;
-            const double mk = (q == 0) ? L.diag : L.diag - near * carry_g;
+            const double wb = (k > 0) ? c.gz * (1.0 + c.hc * s_gf[k]) : 0.0;
+            const double wa = (k < nz - 1) ? c.gz * (1.0 + c.hc * s_gf[k + 1]) : 0.0;
+            const double diag = opsig * (((h0 + s_gc[k] * h1) + wb) + wa);
+            const double near = upper ? -wa : -wb;
+            const double far = upper ? -wb : -wa;
+            const double mk = (q == 0) ? diag : diag - near * carry_g;
             const double fk = (q == 0) ? rp : rp - near * carry_d;
             const bool meet = !upper && q == h - 1;
             if (meet) {
@@ -638,8 +667,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const double sn = block_sum(acc_new, sh);
     const double ss = block_sum(acc_st, sh);
     if (threadIdx.x == 0) {
-        part[(long long)lb * NV_MAX + 0] = sn;
-        part[(long long)lb * NV_MAX + 1] = ss;
+        part[(long long)(0) * pstride + lb] = sn;
+        part[(long long)(1) * pstride + lb] = ss;
     }
 }
 
@@ -650,8 +679,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mod
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
     if (st->status != RUNNING) return;
-    const double rn = sum_partials(in.part, in.nblk_col, 0, sh);
-    const double rs = sum_partials(in.part, in.nblk_col, 1, sh);
+    const double rn = sum_partials(in, in.nblk_col, 0, sh);
+    const double rs = sum_partials(in, in.nblk_col, 1, sh);
     if (threadIdx.x == 0) {
         if (mode == MODE_STEP) decide_step(st, rn, rs, in.hist, in.hist_cap);
         else decide_init(st, rn, rs);
@@ -676,20 +705,32 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
     if ((int)threadIdx.x <= nu) s_ap[threadIdx.x] = in.AP[st->slot[threadIdx.x]];
     __syncthreads();
     const StPos ps = st_pos(in, lb);
+    const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
-    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + plane * ps.k0;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double le[KC];
-    if (ps.valid) stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, le);
-    // every <L(e), L(p^l)> at once: all loads visible to the scheduler
+    stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, le);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+        if (!(ps.col_ok && ps.k0 + kk < nz)) le[kk] = 0.0;
+    // every <L(e), L(p^l)>: one uniform branch per l, its KC loads batched
     double acc[KMAX + 1];
 #pragma unroll
     for (int l = 0; l <= KMAX; ++l) {
         acc[l] = 0.0;
-        if (l <= nu && ps.valid) {
+        if (l <= nu) {
             const T* apl = s_ap[l];
+            double av[KC];
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk)
-                if (ps.k0 + kk < in.g.nz) acc[l] = fma(le[kk], (double)apl[c0 + plane * kk], acc[l]);
+            for (int kk = 0; kk < KC; ++kk) {
+                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                av[kk] = (double)apl[c0 + plane * kq];
+            }
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const bool ok = ps.col_ok && ps.k0 + kk < nz;
+                acc[l] = fma(le[kk], ok ? av[kk] : 0.0, acc[l]);
+            }
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -703,7 +744,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
     __syncthreads();
     if ((int)threadIdx.x <= nu) {
         const int l = threadIdx.x;
-        in.part[(long long)lb * NV_MAX + l] = ((sh[l][0] + sh[l][1]) + sh[l][2]) + sh[l][3];
+        in.part[(long long)(l) * in.pstride + lb] = ((sh[l][0] + sh[l][1]) + sh[l][2]) + sh[l][3];
     }
 }
 
@@ -716,7 +757,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(Table<T> tb)
     if (st->status != RUNNING || !st->active) return;
     const int nu = st->nu;
     for (int l = 0; l <= nu; ++l) {
-        const double s = sum_partials(in.part, in.nblk_st, l, sh);
+        const double s = sum_partials(in, in.nblk_st, l, sh);
         if (threadIdx.x == 0) st->alpha[l] = -s / st->d[l];
     }
     if (threadIdx.x == 0) st->x_dst = (st->x_base == st->x_bak) ? 1 - st->x_base : st->x_base;
@@ -758,59 +799,63 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
     }
     __syncthreads();
     const StPos ps = st_pos(in, lb);
+    const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
-    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j + plane * ps.k0;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    double a[KC], p[KC], xa[KC], r[KC];
+    stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        const long long c = c0 + plane * kq;
+        p[kk] = (double)in.E[c];
+        r[kk] = (double)rv[c];
+        xa[kk] = xupd ? xb[c] : 0.0;
+    }
+#pragma unroll
+    for (int l = 0; l < KMAX; ++l) {
+        if (l <= nu) {
+            const T* pl = s_p[l];
+            const T* apl = s_ap[l];
+            const double al = s_al[l];
+            const double bl = s_be[l];
+            double pv[KC], av[KC];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                pv[kk] = (double)pl[c0 + plane * kq];
+                av[kk] = (double)apl[c0 + plane * kq];
+            }
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                p[kk] = fma(al, pv[kk], p[kk]);
+                a[kk] = fma(al, av[kk], a[kk]);
+                if (xupd) xa[kk] = fma(bl, pv[kk], xa[kk]);
+            }
+        }
+    }
     double acc_num = 0.0, acc_d = 0.0;
-    if (ps.valid) {
-        double a[KC], p[KC], xa[KC], r[KC];
-        stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a);
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const bool ok = ps.k0 + kk < in.g.nz;
-            const long long c = c0 + plane * kk;
-            p[kk] = ok ? (double)in.E[c] : 0.0;
-            r[kk] = ok ? (double)rv[c] : 0.0;
-            xa[kk] = (ok && xupd) ? xb[c] : 0.0;
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        const T ps_ = (T)p[kk];
+        const T as_ = (T)a[kk];
+        if (ok) {
+            const long long c = c0 + plane * (ps.k0 + kk);
+            pout[c] = ps_;
+            apout[c] = as_;
+            if (xupd) xo[c] = xa[kk];
         }
-#pragma unroll
-        for (int l = 0; l < KMAX; ++l) {
-            if (l <= nu) {
-                const T* pl = s_p[l];
-                const T* apl = s_ap[l];
-                const double al = s_al[l];
-                const double bl = s_be[l];
-#pragma unroll
-                for (int kk = 0; kk < KC; ++kk) {
-                    if (ps.k0 + kk < in.g.nz) {
-                        const long long c = c0 + plane * kk;
-                        const double pv = (double)pl[c];
-                        p[kk] = fma(al, pv, p[kk]);
-                        a[kk] = fma(al, (double)apl[c], a[kk]);
-                        if (xupd) xa[kk] = fma(bl, pv, xa[kk]);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            if (ps.k0 + kk < in.g.nz) {
-                const long long c = c0 + plane * kk;
-                const T ps_ = (T)p[kk];
-                const T as_ = (T)a[kk];
-                pout[c] = ps_;
-                apout[c] = as_;
-                if (xupd) xo[c] = xa[kk];
-                const double ad = (double)as_;
-                acc_num = fma(r[kk], ad, acc_num);
-                acc_d = fma(ad, ad, acc_d);
-            }
-        }
+        const double ad = ok ? (double)as_ : 0.0;
+        const double rd = ok ? r[kk] : 0.0;
+        acc_num = fma(rd, ad, acc_num);
+        acc_d = fma(ad, ad, acc_d);
     }
     const double sn = block_sum(acc_num, sh);
     const double sd = block_sum(acc_d, sh);
     if (threadIdx.x == 0) {
-        in.part[(long long)lb * NV_MAX + 0] = sn;
-        in.part[(long long)lb * NV_MAX + 1] = sd;
+        in.part[(long long)(0) * in.pstride + lb] = sn;
+        in.part[(long long)(1) * in.pstride + lb] = sd;
     }
 }
 
@@ -822,8 +867,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int in
     SolveState* st = in.st;
     if (st->status != RUNNING) return;
     if (!init && !st->active) return;
-    const double num = sum_partials(in.part, in.nblk_st, 0, sh);
-    const double dn = sum_partials(in.part, in.nblk_st, 1, sh);
+    const double num = sum_partials(in, in.nblk_st, 0, sh);
+    const double dn = sum_partials(in, in.nblk_st, 1, sh);
     if (threadIdx.x == 0) decide_beta(st, num, dn, init);
 }
 
@@ -838,7 +883,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_finalize_x(Table<T> tb)
     const int lo = st->x_base_nu, hi = st->x_final_hi;
     if (st->x_base == 0 && hi < lo) return;
     const StPos ps = st_pos(in, lb);
-    if (!ps.valid) return;
+    if (!ps.col_ok) return;
     const double* xb = in.X[st->x_base];
     double* xo = in.X[0];
 #pragma unroll
@@ -962,7 +1007,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
     const int lb = blockIdx.x;
     const StPos ps = st_pos(in, lb);
     double an = 0.0, ad = 0.0;
-    if (ps.valid) {
+    if (ps.col_ok) {
         const T* r = in.R[st->r_cur];
         const T* ap = in.AP[st->slot[st->nu]];
         for (int kk = 0; kk < in.kc; ++kk) {
@@ -977,8 +1022,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
     const double sn = block_sum(an, sh);
     const double sd = block_sum(ad, sh);
     if (threadIdx.x == 0) {
-        in.part[(long long)lb * NV_MAX + 0] = sn;
-        in.part[(long long)lb * NV_MAX + 1] = sd;
+        in.part[(long long)(0) * in.pstride + lb] = sn;
+        in.part[(long long)(1) * in.pstride + lb] = sd;
     }
 }
 
@@ -989,8 +1034,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta_dots(Table<T> tb)
     const Inst<T>& in = tb.inst[0];
     SolveState* st = in.st;
     if (!st->ev_ok) return;
-    const double num = sum_partials(in.part, in.nblk_st, 0, sh);
-    const double dn = sum_partials(in.part, in.nblk_st, 1, sh);
+    const double num = sum_partials(in, in.nblk_st, 0, sh);
+    const double dn = sum_partials(in, in.nblk_st, 1, sh);
     if (threadIdx.x == 0) {
         st->beta_num = num;
         st->d_cur = dn;
@@ -1007,7 +1052,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, 
 {
     const Inst<double>& in = tb.inst[0];
     const StPos ps = st_pos(in, blockIdx.x);
-    if (!ps.valid) return;
+    if (!ps.col_ok) return;
     double ax[KC];
     stencil_chunk<double, KC>(in.g, x, ps.i, ps.j, ps.k0, ax);
 #pragma unroll

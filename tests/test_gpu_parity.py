@@ -132,6 +132,26 @@ def test_solve_deterministic(ft):
     s.close()
 
 
+def test_graph_replay_matches_direct_launches(ft):
+    """Steps replayed from a captured graph (several replays, with the
+    solver's own synchronising status reads between them) give bit-identical
+    results to directly launched steps, fault events included."""
+    _say("graphs vs direct")
+    pb = Problem(96, 40, 12, hill_amp=0.8)
+    rhs = I.rhs(pb, 9)
+    plan = [FaultEvent(37, "r", 62, idx=np.array([123])), FaultEvent(70, "ap", 61, idx=np.array([5, 6]))]
+    out = []
+    for graphs in (0, 1, 1):
+        s = ft.Solver(pb, kmax=4, use_graphs=graphs, poll_steps=8)
+        x, st = s.solve(rhs, tol=1e-10, k=4, plan=plan, hist_cap=10000)
+        out.append((x.cpu().numpy(), st))
+        s.close()
+    for x, st in out[1:]:
+        assert np.array_equal(x, out[0][0])
+        assert np.array_equal(st["hist"], out[0][1]["hist"])
+        assert _decisions(st["log"]) == _decisions(out[0][1]["log"])
+
+
 def test_c1_fault_plan(ft, oracle_mod):
     """Bit 62 of one residual entry at step 5: detected at step 5, rolled
     back, and the run then replays the fault-free one exactly."""
