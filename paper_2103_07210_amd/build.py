@@ -34,7 +34,7 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         err = "\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l and l.strip())
         if p.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{err}")
-        if err and verbose:
+        if err:
             print(err, file=sys.stderr)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

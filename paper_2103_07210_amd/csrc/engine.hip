@@ -136,6 +136,13 @@ void set_tiling(ftgcr_handle* h)
 
 size_t elem_bytes(const ftgcr_handle* h) { return h->precision == FTGCR_MIXED ? 4 : 8; }
 
+// Room for block partials of either grid at any levels-per-block (1 level
+// per block is the most blocks), so batched solves may pick their own tiling.
+long long part_stride(const ftgcr_handle* h)
+{
+    return std::max<long long>(h->nblk_col, (long long)h->tx * h->ty * h->geo.nz);
+}
+
 struct Layout {
     size_t vec, xvec, part, hist, total;
 };
@@ -146,7 +153,7 @@ Layout layout(const ftgcr_handle* h)
     const size_t n = (size_t)h->geo.n;
     L.vec = align256(n * elem_bytes(h));
     L.xvec = align256(n * sizeof(double));
-    L.part = align256((size_t)std::max(h->nblk_col, h->nblk_st) * NV_MAX * sizeof(double));
+    L.part = align256((size_t)part_stride(h) * NV_MAX * sizeof(double));
     L.hist = align256((size_t)std::max<long long>(h->opt.hist_cap, 1) * sizeof(double));
     L.total = (size_t)(2 * (h->kmax + 1) + 4) * L.vec + L.xvec + L.part + L.hist;
     return L;
@@ -167,7 +174,7 @@ Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x)
     in.X[0] = x;
     in.X[1] = (double*)p; p += L.xvec;
     in.part = (double*)p; p += L.part;
-    in.pstride = std::max(h->nblk_col, h->nblk_st);
+    in.pstride = part_stride(h);
     in.hist = (double*)p;
     in.hist_cap = h->opt.hist_cap;
     in.rhs = rhs;
@@ -600,6 +607,232 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     return FTGCR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched solve
+// ---------------------------------------------------------------------------
+//
+// Members step together: each launch of a step kernel covers the blocks of
+// every unfinished member (block -> member by a prefix search), and the
+// one-block reductions run one block per member.  All members share one
+// Thomas depth and one stencil tiling.  Finished members are dropped from the
+// launch table at the next status read.
+
+struct BatchTables {
+    Inst<double>* inst = nullptr;   // device
+    int* blk0 = nullptr;            // device: col prefix (n+1), st prefix (n+1)
+    long long* status = nullptr;    // device: 2 per member
+    int cols = 0, sts = 0;
+};
+
+ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins, const std::vector<int>& members,
+                          BatchTables& bt, Table<double>& tb)
+{
+    const int na = (int)members.size();
+    std::vector<Inst<double>> act(na);
+    std::vector<int> pre(2 * (na + 1), 0);
+    for (int q = 0; q < na; ++q) {
+        act[q] = ins[members[q]];
+        pre[q + 1] = pre[q] + act[q].nblk_col;
+        pre[na + 1 + q + 1] = pre[na + 1 + q] + act[q].nblk_st;
+    }
+    HIP_TRY(h0, hipMemcpy(bt.inst, act.data(), na * sizeof(Inst<double>), hipMemcpyHostToDevice));
+    HIP_TRY(h0, hipMemcpy(bt.blk0, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
+    bt.cols = pre[na];
+    bt.sts = pre[2 * na + 1];
+    tb = Table<double>{bt.inst, bt.blk0, bt.blk0 + na + 1, na};
+    return FTGCR_OK;
+}
+
+ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* const* rhs, double* const* x,
+                              const double* tol, int k, const ftgcr_fault_plan* plans, ftgcr_stats* stats)
+{
+    using L = Launch<double>;
+    ftgcr_handle* h0 = hs[0];
+    hipStream_t s = h0->stream;
+    // common tiling: Thomas depth of the deepest member, stencil levels per
+    // block chosen for the largest member
+    int H = 4, kc = 1;
+    long long biggest = -1;
+    for (int m = 0; m < n; ++m) {
+        H = std::max(H, hs[m]->H);
+        if (hs[m]->geo.n > biggest) {
+            biggest = hs[m]->geo.n;
+            kc = hs[m]->kc;
+        }
+    }
+    std::vector<Inst<double>> ins(n);
+    std::vector<std::vector<DevEvent>> evs(n);
+    for (int m = 0; m < n; ++m) {
+        ftgcr_handle* h = hs[m];
+        ins[m] = make_inst<double>(h, rhs[m], x[m]);
+        ins[m].kc = kc;
+        ins[m].tz = (h->geo.nz + kc - 1) / kc;
+        ins[m].nblk_st = ins[m].tx * ins[m].ty * ins[m].tz;
+        ftgcr_status rc = stage_events(h, plans ? &plans[m] : nullptr, evs[m]);
+        if (rc != FTGCR_OK) {
+            if (m) h0->err = h->err;
+            return rc;
+        }
+    }
+    BatchTables bt;
+    auto cleanup = [&]() {
+        if (bt.inst) (void)hipFree(bt.inst);
+        if (bt.blk0) (void)hipFree(bt.blk0);
+        if (bt.status) (void)hipFree(bt.status);
+    };
+    if (hipMalloc(&bt.inst, n * sizeof(Inst<double>)) != hipSuccess ||
+        hipMalloc(&bt.blk0, 2 * (n + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&bt.status, 2 * n * sizeof(long long)) != hipSuccess) {
+        cleanup();
+        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
+    }
+    // full table (members in order) and the per-member single tables used by
+    // the fault-event kernels
+    Inst<double>* all = nullptr;
+    if (hipMalloc(&all, n * sizeof(Inst<double>)) != hipSuccess) {
+        cleanup();
+        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
+    }
+    auto cleanup_all = [&]() {
+        cleanup();
+        (void)hipFree(all);
+    };
+    if (hipMemcpy(all, ins.data(), n * sizeof(Inst<double>), hipMemcpyHostToDevice) != hipSuccess) {
+        cleanup_all();
+        return fail(h0, FTGCR_E_HIP, "batch table upload failed");
+    }
+    std::vector<int> members(n);
+    for (int m = 0; m < n; ++m) members[m] = m;
+    // the full table keeps its own prefix arrays (the launch table is
+    // compacted in place as members finish)
+    int* blk0_all = nullptr;
+    std::vector<int> pre_all(2 * (n + 1), 0);
+    for (int m = 0; m < n; ++m) {
+        pre_all[m + 1] = pre_all[m] + ins[m].nblk_col;
+        pre_all[n + 1 + m + 1] = pre_all[n + 1 + m] + ins[m].nblk_st;
+    }
+    if (hipMalloc(&blk0_all, pre_all.size() * sizeof(int)) != hipSuccess ||
+        hipMemcpy(blk0_all, pre_all.data(), pre_all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        if (blk0_all) (void)hipFree(blk0_all);
+        cleanup_all();
+        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
+    }
+    auto cleanup_full = [&]() {
+        cleanup_all();
+        (void)hipFree(blk0_all);
+    };
+    const Table<double> tb_all{all, blk0_all, blk0_all + n + 1, n};
+    const int sts_all = pre_all[2 * n + 1];
+    Table<double> tb{};
+    ftgcr_status rc = upload_batch(h0, ins, members, bt, tb);
+    if (rc != FTGCR_OK) {
+        cleanup_full();
+        return rc;
+    }
+    auto single = [&](int m) { return Table<double>{all + m, hs[m]->blk0, hs[m]->blk0 + 2, 1}; };
+
+    hipEvent_t e0 = h0->ev_start, e1 = h0->ev_stop;
+    (void)hipEventRecord(e0, s);
+    for (int m = 0; m < n; ++m)
+        L::init_state(single(m), k, hs[m]->opt.ft, 0, hs[m]->opt.max_steps, tol[m] * tol[m], 1, 1, s);
+    L::residual(tb, bt.sts, kc, 1, 1, s);
+    L::update_thomas(tb, bt.cols, H, 1, s);
+    L::finish_col(tb, 1, s);
+    L::dir_update(tb, bt.sts, kc, 1, s);
+    L::finish_beta(tb, 1, s);
+
+    const int chunk = std::max(1, h0->opt.poll_steps);
+    long long launched = 0, max_cap = 0;
+    for (int m = 0; m < n; ++m) max_cap = std::max<long long>(max_cap, hs[m]->opt.max_steps);
+    std::vector<size_t> evp(n, 0);
+    std::vector<long long> host_status(2 * n);
+    while (!members.empty()) {
+        // fault events of the next step, member by member
+        bool any_event = false;
+        for (int m : members) {
+            while (evp[m] < evs[m].size() && evs[m][evp[m]].step <= launched) ++evp[m];
+            while (evp[m] < evs[m].size() && evs[m][evp[m]].step == launched + 1) {
+                const DevEvent& ev = evs[m][evp[m]++];
+                const Table<double> t1 = single(m);
+                const long long nn = hs[m]->geo.n;
+                L::event_prep(t1, ev.vec, s);
+                L::event_copy(t1, (int)std::min<long long>((nn + 255) / 256, 8192), s);
+                L::event_inject(t1, (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192)),
+                                ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
+                if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) L::beta_dots(t1, ins[m].nblk_st, s);
+                any_event = true;
+            }
+        }
+        long long cnt = any_event ? 1 : chunk;
+        for (int m : members)
+            if (evp[m] < evs[m].size()) cnt = std::min<long long>(cnt, std::max<long long>(1, evs[m][evp[m]].step - 1 - launched));
+        for (long long q = 0; q < cnt; ++q) {
+            L::update_thomas(tb, bt.cols, H, 0, s);
+            L::finish_col(tb, 0, s);
+            L::stencil_dots(tb, bt.sts, kc, s);
+            L::finish_alpha(tb, s);
+            L::dir_update(tb, bt.sts, kc, 0, s);
+            L::finish_beta(tb, 0, s);
+        }
+        launched += cnt;
+        L::gather_status(tb, bt.status, s);
+        if (hipMemcpyAsync(host_status.data(), bt.status, 2 * members.size() * sizeof(long long),
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            cleanup_full();
+            return fail(h0, FTGCR_E_HIP, "batch status read failed");
+        }
+        std::vector<int> still;
+        for (size_t q = 0; q < members.size(); ++q)
+            if (host_status[2 * q] == RUNNING) still.push_back(members[q]);
+        if (still.size() != members.size()) {
+            members.swap(still);
+            if (!members.empty()) {
+                rc = upload_batch(h0, ins, members, bt, tb);
+                if (rc != FTGCR_OK) {
+                    cleanup_full();
+                    return rc;
+                }
+            }
+        }
+        if (launched > max_cap + chunk + 16) {
+            cleanup_full();
+            return fail(h0, FTGCR_E_HIP, "batched step loop did not terminate");
+        }
+    }
+    L::finalize_x(tb_all, sts_all, kc, s);
+    L::residual(tb_all, sts_all, kc, 0, 0, s);
+    (void)hipEventRecord(e1, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        cleanup_full();
+        return fail(h0, FTGCR_E_HIP, "batch synchronisation failed");
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    for (int m = 0; m < n; ++m) {
+        ftgcr_handle* h = hs[m];
+        if (hipMemcpy(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost) != hipSuccess) {
+            cleanup_full();
+            return fail(h0, FTGCR_E_HIP, "batch state read failed");
+        }
+        if (stats) {
+            fill_stats(h, *h->st_host, 0, ms, &stats[m]);
+            if (stats[m].hist && stats[m].hist_cap > 0) {
+                const long long nh = std::min<long long>(std::min<long long>(h->st_host->s, h->opt.hist_cap),
+                                                         stats[m].hist_cap);
+                if (nh > 0 && hipMemcpy(stats[m].hist, ins[m].hist, (size_t)nh * sizeof(double),
+                                        hipMemcpyDeviceToHost) != hipSuccess) {
+                    cleanup_full();
+                    return fail(h0, FTGCR_E_HIP, "batch history read failed");
+                }
+                stats[m].hist_len = nh;
+            }
+        }
+    }
+    cleanup_full();
+    return FTGCR_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -750,11 +983,19 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
 {
     if (!hs || n < 1 || !rhs || !x || !tol) return FTGCR_E_INVALID;
     for (int m = 0; m < n; ++m) {
-        ftgcr_status rc = ftgcr_solve(hs[m], rhs[m], x[m], tol[m], k, plans ? &plans[m] : nullptr,
-                                      stats ? &stats[m] : nullptr);
-        if (rc != FTGCR_OK) return rc;
+        ftgcr_handle* h = hs[m];
+        if (!h) return FTGCR_E_INVALID;
+        if (h->precision != FTGCR_FP64) return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are FP64 only");
+        if (!rhs[m] || !x[m]) return fail(hs[0], FTGCR_E_INVALID, "rhs or x is NULL");
+        if (!(tol[m] > 0) || !std::isfinite(tol[m])) return fail(hs[0], FTGCR_E_INVALID, "tol must be finite and > 0");
+        if (k < 1 || k > h->kmax) return fail(hs[0], FTGCR_E_INVALID, "k must be in [1, kmax] of every member");
+        if (!h->ws || h->ws_bytes < layout(h).total) return fail(hs[0], FTGCR_E_WORKSPACE, "member without a large enough workspace");
+        if (h->device != hs[0]->device) return fail(hs[0], FTGCR_E_INVALID, "members on different devices");
+        for (int q = 0; q < m; ++q)
+            if (hs[q] == h) return fail(hs[0], FTGCR_E_INVALID, "a handle appears twice in the batch");
     }
-    return FTGCR_OK;
+    HIP_TRY(hs[0], hipSetDevice(hs[0]->device));
+    return solve_batch_impl(hs, n, rhs, x, tol, k, plans, stats);
 }
 
 ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, int32_t cap, int32_t* n_out)

@@ -145,6 +145,7 @@ template <typename T> struct Launch {
     static void event_inject(const Table<T>& tb, int grid, const long long* idx, const unsigned char* bits,
                              long long count, long long start, int bit, hipStream_t s);
     static void beta_dots(const Table<T>& tb, int total_st_blocks, hipStream_t s);
+    static void gather_status(const Table<T>& tb, long long* out, hipStream_t s);
     // parity entry points (FP64 only)
     static void debug_apply_A(const Table<T>& tb, int total_st_blocks, int kc, const double* in, double* out, hipStream_t s);
     static void debug_pinv(const Table<T>& tb, int total_col_blocks, int H, const double* in, double* out, hipStream_t s);

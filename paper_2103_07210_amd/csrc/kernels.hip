@@ -1212,6 +1212,24 @@ void Launch<double>::debug_pinv(const Table<double>& tb, int total, int H, const
                                          0, s, tb, in, out));
 }
 
+// Status and step count of every instance into a small device array (one
+// read-back per poll of a batched solve).
+template <typename T>
+__global__ void k_gather_status(Table<T> tb, long long* out)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= tb.n) return;
+    const SolveState* st = tb.inst[m].st;
+    out[2 * m] = st->status;
+    out[2 * m + 1] = st->s;
+}
+
+template <typename T>
+void Launch<T>::gather_status(const Table<T>& tb, long long* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_status<T>, dim3((tb.n + 63) / 64), dim3(64), 0, s, tb, out);
+}
+
 template struct Launch<double>;
 template struct Launch<float>;
 

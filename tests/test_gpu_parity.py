@@ -313,3 +313,54 @@ def test_ft_off_matches_plain_gcr(ft, oracle_mod):
     assert st["status"] == so["status"]
     assert abs(st["steps_executed"] - so["steps_executed"]) <= 1
     s.close()
+
+
+def test_batch_matches_oracle_per_member(ft, oracle_mod):
+    """Several problems of different sizes and hills solved by one batched
+    launch sequence: every member converges as the oracle does (steps +-1,
+    the same decisions, x within 1e-10 at equal step counts)."""
+    shapes = [(64, 32, 8), (96, 48, 12), (64, 32, 8), (128, 64, 16), (70, 9, 5), (96, 48, 12)]
+    pbs = [Problem(*sh, hill_lon=0.4 * m, hill_lat=0.3 - 0.1 * m, hill_amp=0.2 + 0.15 * m)
+           for m, sh in enumerate(shapes)]
+    rhs = [I.rhs(pb, 40 + m) for m, pb in enumerate(pbs)]
+    plans = [[], [FaultEvent(6, "r", 62, idx=np.array([17]))], [], [FaultEvent(9, "ap", 62, idx=np.array([3]))],
+             [FaultEvent(2, "x", 50, idx=np.array([4]))], []]
+    tols = [1e-10, 1e-10, 1e-9, 1e-10, 1e-10, 1e-8]
+    solvers = [ft.Solver(pb, kmax=3) for pb in pbs]
+    _say("batch of", len(pbs))
+    xs, sts = ft.solve_batch(solvers, rhs, tols=tols, k=3, plans=plans)
+    for m, pb in enumerate(pbs):
+        o = oracle_mod.Oracle(pb)
+        xo, so, logo, _ = o.solve(rhs[m], tol=tols[m], k=3, plan=plans[m])
+        st = sts[m]
+        assert st["status"] == ft.CONVERGED, (m, st)
+        assert abs(st["steps_executed"] - so["steps_executed"]) <= 1, m
+        assert _decisions(st["log"]) == _decisions(logo), m
+        xe, _, _, _ = o.solve(rhs[m], tol=tols[m] * 1e-3, k=3, plan=plans[m], max_steps=st["steps_executed"])
+        assert _rel(xs[m].cpu().numpy(), xe) <= 1e-10, m
+        assert st["rel_res_true"] <= 1.01 * tols[m] or plans[m]
+    for s in solvers:
+        s.close()
+
+
+def test_batch_ensemble_workload(ft, oracle_mod):
+    """The 64-member ensemble (sizes drawn from 64x32x8 .. 256x128x32, hill
+    centre and amplitude per member, 6 members with one bit-62 flip in r):
+    every member converges to the true residual tolerance; the faulty small
+    members take the oracle's decisions."""
+    members = I.ensemble(64, seed=I.SEEDS["c4_table"])
+    solvers = [ft.Solver(mb.problem, kmax=3) for mb in members]
+    rhs = [I.rhs(mb.problem, mb.rhs_seed) for mb in members]
+    _say("ensemble 64")
+    xs, sts = ft.solve_batch(solvers, rhs, tols=[1e-10] * 64, k=3, plans=[mb.plan for mb in members])
+    for m, mb in enumerate(members):
+        assert sts[m]["status"] == ft.CONVERGED, m
+        assert sts[m]["rel_res_true"] <= 2e-10, (m, sts[m]["rel_res_true"])
+        if mb.plan and mb.problem.n <= 131072:
+            o = oracle_mod.Oracle(mb.problem)
+            _, so, logo, _ = o.solve(rhs[m], tol=1e-10, k=3, plan=mb.plan)
+            assert _decisions(sts[m]["log"]) == _decisions(logo), m
+            assert abs(sts[m]["steps_executed"] - so["steps_executed"]) <= 1
+    assert sum(st["events_applied"] for st in sts) >= 1
+    for s in solvers:
+        s.close()
