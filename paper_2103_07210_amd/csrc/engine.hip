@@ -552,6 +552,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     const bool mixed = h->precision == FTGCR_MIXED;
     const long long max_steps = h->opt.max_steps;
     int refinements = 0;
+    int inner_outcome_final = FTGCR_CONVERGED;
 
     HIP_TRY(h, hipEventRecord(h->ev_start, s));
     if (!mixed) {
@@ -564,8 +565,13 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     } else {
         // iterative refinement: FP64 true residual outside, FT-GCR with
         // binary32 vectors inside, the correction accumulated into FP64 x
-        L::init_state(tb, k, h->opt.ft, 1, max_steps, 0.0, 1, 1, s);
+        bool first = true;
+        int inner_outcome = FTGCR_CONVERGED;
         while (true) {
+            // a fresh round state first (it names the buffer the true
+            // residual is written to), then r_t = A x - R in FP64
+            L::init_state(tb, k, h->opt.ft, 1, max_steps, 0.0, first ? 1 : 0, 1, s);
+            first = false;
             L::residual(tb, h->nblk_st, h->kc, 1, 0, s);
             rc = run.read_state();
             if (rc != FTGCR_OK) return rc;
@@ -576,13 +582,15 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
             tau = std::min(tau, 0.5);
             const long long cap = std::min<long long>(max_steps, hs.s + h->opt.inner_max_steps);
             const long long s0 = hs.s;
-            L::init_state(tb, k, h->opt.ft, 1, cap, tau * tau, 0, 1, s);
-            L::set_threshold(tb, 1, s);
+            L::set_round(tb, tau * tau, cap, s);
             run.start_round();
             rc = run.run_steps(s0, cap, evs);
             if (rc != FTGCR_OK) return rc;
             L::finalize_x(tb, h->nblk_st, h->kc, s);
             refinements += 1;
+            inner_outcome = h->st_host->status;   // from the last status read
+            inner_outcome_final = inner_outcome;
+            if (inner_outcome == FTGCR_BREAKDOWN) break;
         }
     }
     // FP64 true residual of the returned x
@@ -596,7 +604,8 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     if (mixed) {
         // the outer loop decides convergence on the true residual
         if (st.rt2 <= tol * tol * st.RR) st.status = FTGCR_CONVERGED;
-        else if (st.status == FTGCR_CONVERGED) st.status = FTGCR_MAX_STEPS;
+        else if (inner_outcome_final == FTGCR_BREAKDOWN) st.status = FTGCR_BREAKDOWN;
+        else st.status = FTGCR_MAX_STEPS;
     }
     fill_stats(h, st, refinements, ms, stats);
     if (stats && stats->hist && stats->hist_cap > 0) {

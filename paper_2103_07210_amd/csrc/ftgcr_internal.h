@@ -27,7 +27,7 @@ constexpr int COLS_PER_BLOCK = 128;
 constexpr int ST_TX = 64;
 constexpr int ST_TY = 4;
 constexpr int ST_THREADS = ST_TX * ST_TY;
-constexpr int RED_THREADS = 256;
+constexpr int RED_THREADS = 1024;
 
 struct DetectRec {
     long long step;
@@ -130,7 +130,7 @@ struct Table {
 template <typename T> struct Launch {
     static void init_state(const Table<T>& tb, int k, int ft, int mixed, long long max_steps, double tol2,
                            int reset_counters, int grid, hipStream_t s);
-    static void set_threshold(const Table<T>& tb, int n, hipStream_t s);
+    static void set_round(const Table<T>& tb, double tol2, long long max_steps, hipStream_t s);
     static void residual(const Table<T>& tb, int total_st_blocks, int kc, int store, int set_T, hipStream_t s);
     static void update_thomas(const Table<T>& tb, int total_col_blocks, int H, int mode, hipStream_t s);
     static void finish_col(const Table<T>& tb, int mode, hipStream_t s);

@@ -63,15 +63,45 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-// Fixed-order sum of value q over an instance's block partials (stored
-// value-major, so a value's partials are contiguous).
+// Fixed-order sums of values 0..nv-1 over an instance's block partials
+// (value-major: a value's partials are contiguous), by one RED_THREADS block:
+// thread t adds blocks t, t + RED_THREADS, ... in order, then the waves are
+// summed in a fixed order.  Every value's loads are independent, so each
+// pass over the blocks is one round trip for all values.  out[q] is valid in
+// every thread.
 template <typename T>
-__device__ __forceinline__ double sum_partials(const Inst<T>& in, int nblk, int q, double* sh)
+__device__ __forceinline__ void sum_partials(const Inst<T>& in, int nblk, int nv, double* out)
 {
-    const double* part = in.part + (long long)q * in.pstride;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RED_THREADS) acc += part[b];
-    return block_sum(acc, sh);
+    constexpr int NW = RED_THREADS / 64;
+    __shared__ double sh[NV_MAX][NW];
+    __shared__ double res[NV_MAX];
+    const double* part = in.part;
+    const long long stride = in.pstride;
+    double acc[NV_MAX];
+#pragma unroll
+    for (int q = 0; q < NV_MAX; ++q) acc[q] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
+#pragma unroll
+        for (int q = 0; q < NV_MAX; ++q)
+            if (q < nv) acc[q] += part[(long long)q * stride + b];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV_MAX; ++q) {
+        if (q < nv) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) sh[q][w] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        double t = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) t += sh[threadIdx.x][ww];
+        res[threadIdx.x] = t;
+    }
+    __syncthreads();
+    for (int q = 0; q < nv; ++q) out[q] = res[q];
 }
 
 // Per-column constants: hill_amp * h at the five horizontal positions and
@@ -285,15 +315,17 @@ __global__ void k_init_state(Table<T> tb, int k, int ft, int mixed, long long ma
     st->ev_ok = 0;
 }
 
-// Exit threshold of the current round: tol^2 <R,R> (FP64 solve) or
-// tau^2 <r_t, r_t> (inner round of the mixed-precision refinement).
+// Tolerance and step cap of an inner round of the mixed-precision
+// refinement: exit when <r,r> <= tau^2 <r_t, r_t>.
 template <typename T>
-__global__ void k_set_threshold(Table<T> tb)
+__global__ void k_set_round(Table<T> tb, double tol2, long long max_steps)
 {
     const int m = blockIdx.x;
     if (m >= tb.n || threadIdx.x != 0) return;
     SolveState* st = tb.inst[m].st;
-    st->T = st->tol2 * (st->mixed ? st->rt2 : st->RR);
+    st->tol2 = tol2;
+    st->max_steps = max_steps;
+    st->T = tol2 * (st->mixed ? st->rt2 : st->RR);
 }
 
 // r = A x - R (x = caller's FP64 iterate), stored in R[r_dst] when `store`;
@@ -339,11 +371,11 @@ __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_residual(Table<T> tb, int set_T)
 {
-    __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
-    const double RR = sum_partials(in, in.nblk_st, 0, sh);
-    const double rt2 = sum_partials(in, in.nblk_st, 1, sh);
+    double v[2];
+    sum_partials(in, in.nblk_st, 2, v);
+    const double RR = v[0], rt2 = v[1];
     if (threadIdx.x == 0) {
         st->RR = RR;
         st->rt2 = rt2;
@@ -507,9 +539,14 @@ __device__ void decide_beta(SolveState* st, double num, double dn, int init)
 template <typename T, int H, int mode>
 __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, const T* dbg_in, T* dbg_out)
 {
+    // The column solve runs in the storage precision: FP64 for FP64 solves;
+    // binary32 for the mixed form, where e = P^{-1} r only has to be a fixed
+    // preconditioner application (L(e) is formed from the stored e).  The
+    // update r+ = r + beta L(p) and both norms stay FP64.
+    using CT = T;
     __shared__ double sh[4];
-    __shared__ double s_gc[2 * H];
-    __shared__ double s_gf[2 * H + 1];
+    __shared__ CT s_gc[2 * H];
+    __shared__ CT s_gf[2 * H + 1];
     const int m = find_inst(tb.blk0_col, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_col[m];
@@ -524,8 +561,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const int nx = g.nx, nz = g.nz, ncols = g.ncols;
     const double opsig = g.opsig;
     // vertical decay tables in LDS (LDS reads do not queue behind stores)
-    for (int t = threadIdx.x; t < nz; t += blockDim.x) s_gc[t] = g.gc[t];
-    for (int t = threadIdx.x; t <= nz; t += blockDim.x) s_gf[t] = g.gf[t];
+    for (int t = threadIdx.x; t < nz; t += blockDim.x) s_gc[t] = (CT)g.gc[t];
+    for (int t = threadIdx.x; t <= nz; t += blockDim.x) s_gf[t] = (CT)g.gf[t];
+    const CT opsig_c = (CT)opsig;
     const T* rin;
     const T* ap;
     T* rout;
@@ -566,8 +604,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // horizontal part of the diagonal: sum of the four side weights is
     // h0 + g_k h1 with per-column constants (fewer operations per level than
     // forming the four weights; equal up to rounding)
-    const double h0 = ((c.gx + c.gx) + c.gys) + c.gyn;
-    const double h1 = (c.gx * (c.hw + c.he) + c.gys * c.hs) + c.gyn * c.hn;
+    const CT h0 = (CT)(((c.gx + c.gx) + c.gys) + c.gyn);
+    const CT h1 = (CT)((c.gx * (c.hw + c.he) + c.gys * c.hs) + c.gyn * c.hn);
+    const CT gz = (CT)c.gz, hc = (CT)c.hc;
 
     // The half column streams in chunks of CH levels, each chunk's loads
     // issued one chunk ahead of its elimination (a two-stage software
@@ -580,22 +619,26 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // u_k, far a_k).
     constexpr int CH = H < 8 ? H : 8;
     constexpr int NCH = H / CH;
-    double bufr[2][CH], bufa[2][CH];
-    double de[H], ga[H];
+    T bufr[2][CH], bufa[2][CH];
+    CT de[H], ga[H];
     double acc_new = 0.0, acc_st = 0.0;
-    double carry_g = 0.0, carry_d = 0.0;
-    double mm = 1.0, ff = 0.0, uu = 0.0;   // meeting row of the lower lane
+    CT carry_g = 0, carry_d = 0;
+    CT mm = 1, ff = 0, uu = 0;   // meeting row of the lower lane
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
         int k = upper ? nz - 1 - t : t;
         k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
         const long long o = (long long)colc + plane * k;
-        bufr[0][t] = (double)rin[o];
-        bufa[0][t] = (mode == MODE_STEP) ? (double)ap[o] : 0.0;
+        bufr[0][t] = rin[o];
+        bufa[0][t] = (mode == MODE_STEP) ? ap[o] : T(0);
     }
 #pragma unroll
     for (int cb = 0; cb < NCH; ++cb) {
         const int b = cb & 1;
+        // keep the pipeline depth at one chunk: without this fence the
+        // scheduler hoists every chunk's loads and the half column's raw
+        // values all sit in registers at once (occupancy 1)
+        __builtin_amdgcn_sched_barrier(0);
         if (cb + 1 < NCH) {
 #pragma unroll
             for (int t = 0; t < CH; ++t) {
@@ -603,8 +646,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
                 int k = upper ? nz - 1 - q : q;
                 k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
                 const long long o = (long long)colc + plane * k;
-                bufr[b ^ 1][t] = (double)rin[o];
-                bufa[b ^ 1][t] = (mode == MODE_STEP) ? (double)ap[o] : 0.0;
+                bufr[b ^ 1][t] = rin[o];
+                bufa[b ^ 1][t] = (mode == MODE_STEP) ? ap[o] : T(0);
             }
         }
 #pragma unroll
@@ -613,30 +656,32 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
             const bool mine = q < nmine;
             int k = upper ? nz - 1 - q : q;
             k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
-            const double v = (mode == MODE_STEP) ? fma(beta, bufa[b][t], bufr[b][t]) : bufr[b][t];
+            const double v = (mode == MODE_STEP) ? fma(beta, (double)bufa[b][t], (double)bufr[b][t])
+                                                 : (double)bufr[b][t];
             const T sv = (T)v;
             const double rp = (double)sv;
+            const CT rc = (CT)sv;
             if (mine && valid) {
                 if (mode == MODE_STEP) rout[(long long)colc + plane * k] = sv;
                 acc_new = fma(v, v, acc_new);
                 acc_st = fma(rp, rp, acc_st);
             }
-            const double wb = (k > 0) ? c.gz * (1.0 + c.hc * s_gf[k]) : 0.0;
-            const double wa = (k < nz - 1) ? c.gz * (1.0 + c.hc * s_gf[k + 1]) : 0.0;
-            const double diag = opsig * (((h0 + s_gc[k] * h1) + wb) + wa);
-            const double near = upper ? -wa : -wb;
-            const double far = upper ? -wb : -wa;
-            const double mk = (q == 0) ? diag : diag - near * carry_g;
-            const double fk = (q == 0) ? rp : rp - near * carry_d;
+            const CT wb = (k > 0) ? gz * (CT(1) + hc * s_gf[k]) : CT(0);
+            const CT wa = (k < nz - 1) ? gz * (CT(1) + hc * s_gf[k + 1]) : CT(0);
+            const CT diag = opsig_c * (((h0 + s_gc[k] * h1) + wb) + wa);
+            const CT near = upper ? -wa : -wb;
+            const CT far = upper ? -wb : -wa;
+            const CT mk = (q == 0) ? diag : diag - near * carry_g;
+            const CT fk = (q == 0) ? rc : rc - near * carry_d;
             const bool meet = !upper && q == h - 1;
             if (meet) {
                 mm = mk;
                 ff = fk;
                 uu = far;
             }
-            const double inv = 1.0 / mk;
-            const double g_new = far * inv;
-            const double d_new = fk * inv;
+            const CT inv = CT(1) / mk;
+            const CT g_new = far * inv;
+            const CT d_new = fk * inv;
             if (mine) {
                 carry_g = meet ? carry_g : g_new;
                 carry_d = meet ? carry_d : d_new;
@@ -646,13 +691,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
         }
     }
     // meeting row: the lower lane gets (zeta_h, eps_h) from its upper partner
-    const double zx = __shfl_xor(carry_g, 32);
-    const double ex = __shfl_xor(carry_d, 32);
-    const double xm = (ff - uu * ex) / (mm - uu * zx);
-    const double xl = __shfl_xor(xm, 32);
+    const CT zx = __shfl_xor(carry_g, 32);
+    const CT ex = __shfl_xor(carry_d, 32);
+    const CT xm = (ff - uu * ex) / (mm - uu * zx);
+    const CT xl = __shfl_xor(xm, 32);
     // back-substitution: lower lane from level h-2 down to 0 (after storing
     // the meeting value at h-1), upper lane from level h up to nz-1
-    double xv = upper ? xl : xm;
+    CT xv = upper ? xl : xm;
     if (valid && !upper) eout[(long long)colc + plane * (h - 1)] = (T)xm;
     const int nback = upper ? nup : h - 1;
 #pragma unroll
@@ -675,12 +720,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mode)
 {
-    __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
     if (st->status != RUNNING) return;
-    const double rn = sum_partials(in, in.nblk_col, 0, sh);
-    const double rs = sum_partials(in, in.nblk_col, 1, sh);
+    double v[2];
+    sum_partials(in, in.nblk_col, 2, v);
+    const double rn = v[0], rs = v[1];
     if (threadIdx.x == 0) {
         if (mode == MODE_STEP) decide_step(st, rn, rs, in.hist, in.hist_cap);
         else decide_init(st, rn, rs);
@@ -751,15 +796,14 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(Table<T> tb)
 {
-    __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
     if (st->status != RUNNING || !st->active) return;
     const int nu = st->nu;
-    for (int l = 0; l <= nu; ++l) {
-        const double s = sum_partials(in, in.nblk_st, l, sh);
-        if (threadIdx.x == 0) st->alpha[l] = -s / st->d[l];
-    }
+    double v[NV_MAX];
+    sum_partials(in, in.nblk_st, nu + 1, v);
+    if (threadIdx.x == 0)
+        for (int l = 0; l <= nu; ++l) st->alpha[l] = -v[l] / st->d[l];
     if (threadIdx.x == 0) st->x_dst = (st->x_base == st->x_bak) ? 1 - st->x_base : st->x_base;
 }
 
@@ -862,13 +906,13 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int init)
 {
-    __shared__ double sh[4];
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
     if (st->status != RUNNING) return;
     if (!init && !st->active) return;
-    const double num = sum_partials(in, in.nblk_st, 0, sh);
-    const double dn = sum_partials(in, in.nblk_st, 1, sh);
+    double v[2];
+    sum_partials(in, in.nblk_st, 2, v);
+    const double num = v[0], dn = v[1];
     if (threadIdx.x == 0) decide_beta(st, num, dn, init);
 }
 
@@ -1030,12 +1074,12 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_beta_dots(Table<T> tb)
 {
-    __shared__ double sh[4];
     const Inst<T>& in = tb.inst[0];
     SolveState* st = in.st;
     if (!st->ev_ok) return;
-    const double num = sum_partials(in, in.nblk_st, 0, sh);
-    const double dn = sum_partials(in, in.nblk_st, 1, sh);
+    double v[2];
+    sum_partials(in, in.nblk_st, 2, v);
+    const double num = v[0], dn = v[1];
     if (threadIdx.x == 0) {
         st->beta_num = num;
         st->d_cur = dn;
@@ -1102,9 +1146,9 @@ void Launch<T>::init_state(const Table<T>& tb, int k, int ft, int mixed, long lo
 }
 
 template <typename T>
-void Launch<T>::set_threshold(const Table<T>& tb, int n, hipStream_t s)
+void Launch<T>::set_round(const Table<T>& tb, double tol2, long long max_steps, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_threshold<T>, dim3(n), dim3(64), 0, s, tb);
+    hipLaunchKernelGGL(k_set_round<T>, dim3(tb.n), dim3(64), 0, s, tb, tol2, max_steps);
 }
 
 template <typename T>

@@ -364,3 +364,41 @@ def test_batch_ensemble_workload(ft, oracle_mod):
     assert sum(st["events_applied"] for st in sts) >= 1
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("shape,k", [((64, 32, 8), 3), ((128, 64, 16), 4), ((100, 7, 5), 4)])
+def test_mixed_precision_reaches_true_residual(ft, oracle_mod, shape, k):
+    """Mixed form: binary32 vectors inside, FP64 true residual outside.  The
+    returned x meets the tolerance on the FP64 true residual (checked with
+    the oracle's operator), and is as close to the oracle's FP64 solution as
+    that residual allows (kappa ~ 2e3 for this shift)."""
+    _say("mixed", shape, k)
+    pb = Problem(*shape, hill_amp=0.6)
+    rhs = I.rhs(pb, 21)
+    tol = 1e-8
+    s = ft.Solver(pb, "mixed", kmax=k)
+    x, st = s.solve(rhs, tol=tol, k=k)
+    assert st["status"] == ft.CONVERGED and st["refinements"] >= 1
+    o = oracle_mod.Oracle(pb)
+    xg = x.cpu().numpy()
+    true = o.true_residual(xg, rhs)
+    assert true <= tol * 1.001, true
+    assert abs(true - st["rel_res_true"]) <= 1e-3 * tol
+    xo, so, _, _ = o.solve(rhs, tol=1e-12, k=k)
+    assert _rel(xg, xo) <= 2.1e3 * tol
+    s.close()
+
+
+def test_mixed_precision_detects_r_fault(ft):
+    """A bit-30 flip (binary32 exponent MSB) of a residual entry below 1 in
+    magnitude is a spike near 1e38 whose FP64 square does not overflow: the
+    norm jumps and the detector fires; the solve still meets the tolerance."""
+    _say("mixed fault")
+    pb = I.C1
+    rhs = I.rhs(pb, 1)
+    s = ft.Solver(pb, "mixed", kmax=3)
+    x, st = s.solve(rhs, tol=1e-8, k=3, plan=[FaultEvent(12, "r", 30, idx=np.array([200]))])
+    assert st["events_applied"] == 1 and st["detections"] >= 1
+    assert st["log"][0]["step"] == 12
+    assert st["status"] == ft.CONVERGED and st["rel_res_true"] <= 1e-8
+    s.close()
