@@ -72,9 +72,10 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter passes: one FP64 solve and the 1 GiB copy probe only")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member batched ensemble timing")
     args = ap.parse_args()
     if args.profile_run:
-        args.steps, args.warmup, args.no_cpu, args.mixed_steps = 1, 0, True, 0
+        args.steps, args.warmup, args.no_cpu, args.mixed_steps, args.no_ensemble = 1, 0, True, 0, True
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a design only "
                                    "(horizontal column blocks, see the design notes); run with --gpus 1"}))
@@ -95,6 +96,8 @@ def main():
     print(f"[bench] grid {GRID} N={n} k={K} tol={TOL}", flush=True)
 
     s64 = ftgcr.Solver(pb, "fp64", kmax=K, poll_steps=32)
+    kc64 = s64.autotune(rhs, k=K, steps=24) if not args.profile_run else s64.options()["levels_per_block"]
+    print(f"[bench] fp64 stencil tiling: {kc64} levels per block", flush=True)
     for _ in range(args.warmup):
         x.zero_()
         s64.solve(rhs, x, tol=TOL, k=K)
@@ -160,6 +163,7 @@ def main():
     mixed = None
     if args.mixed_steps > 0:
         sm = ftgcr.Solver(pb, "mixed", kmax=K, poll_steps=32)
+        kcm = sm.autotune(rhs, k=K, steps=24)
         xm = torch.zeros_like(rhs)
         sm.solve(rhs, xm, tol=TOL, k=K)
         torch.cuda.synchronize()
@@ -179,7 +183,37 @@ def main():
         mixed = {"fp64": fp64_ms, "mixed": mixed_med, "speedup": fp64_ms / mixed_med,
                  "fp64_true_residual": stats["rel_res_true"], "mixed_true_residual": mstats["rel_res_true"],
                  "mixed_inner_steps": mstats["steps_executed"], "mixed_refinements": mstats["refinements"],
-                 "mixed_vs_fp64_solution_rel_diff": mixed_err}
+                 "mixed_vs_fp64_solution_rel_diff": mixed_err, "mixed_levels_per_block": kcm}
+
+    # 64-member ensemble (sizes 64x32x8 .. 256x128x32, 6 members with a
+    # fault): one batched launch sequence against the members one by one
+    ensemble = None
+    if not args.no_ensemble:
+        members = I.ensemble(64, seed=I.SEEDS["c4_table"])
+        solvers = [ftgcr.Solver(mb.problem, "fp64", kmax=3, poll_steps=32) for mb in members]
+        erhs = [torch.from_numpy(I.rhs(mb.problem, mb.rhs_seed)).cuda() for mb in members]
+        plans = [mb.plan for mb in members]
+        ftgcr.solve_batch(solvers, erhs, tols=[1e-10] * 64, k=3, plans=plans)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, bst = ftgcr.solve_batch(solvers, erhs, tols=[1e-10] * 64, k=3, plans=plans)
+        torch.cuda.synchronize()
+        batched_ms = (time.perf_counter() - t1) * 1e3
+        t1 = time.perf_counter()
+        for sv, r, pl in zip(solvers, erhs, plans):
+            sv.solve(r, tol=1e-10, k=3, plan=pl)
+        torch.cuda.synchronize()
+        seq_ms = (time.perf_counter() - t1) * 1e3
+        steps_all = sum(b["steps_executed"] for b in bst)
+        points = sum(mb.problem.n for mb in members)
+        ensemble = {"members": 64, "points": points, "k": 3, "tol": 1e-10,
+                    "batched_ms": batched_ms, "sequential_ms": seq_ms,
+                    "member_steps_total": steps_all, "member_steps_per_s_batched": steps_all / batched_ms * 1e3,
+                    "all_converged": all(b["status"] == 0 for b in bst),
+                    "detections": sum(b["detections"] for b in bst)}
+        print(f"[bench] ensemble: batched {batched_ms:.1f} ms, one by one {seq_ms:.1f} ms", flush=True)
+        for sv in solvers:
+            sv.close()
 
     cpu = None
     if not args.no_cpu:
@@ -200,10 +234,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "FT-GCR(4) FP64 solve to 1e-8, 512x256x64 hill-on-sphere, RHS U[-1,1] seed 3",
-                   "grid": list(GRID), "k": K, "tol": TOL, "steps_per_solve": steps_per_solve},
+                   "grid": list(GRID), "k": K, "tol": TOL, "steps_per_solve": steps_per_solve,
+                   "levels_per_block": kc64},
         "hbm_gbs_algorithmic": whole_gbs,
         "time_to_1e-8_ms": mixed,
         "kernels": kernels,
+        "ensemble_64": ensemble,
         "copy_probe_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic if dom == "dir_update" else None,

@@ -205,6 +205,14 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n,
                                const double* tol, int32_t k,
                                const ftgcr_fault_plan* plans, ftgcr_stats* stats);
 
+/* Autotuner of the stencil tiling (levels of a column per block): times
+ * `steps` steps of this problem for each candidate and keeps the fastest for
+ * this handle (options.levels_per_block = 0) and for every later handle with
+ * the same grid and precision in this process.  x_scratch_dev: FP64 device
+ * buffer of N entries, overwritten.  *chosen (optional) gets the choice. */
+ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_scratch_dev, int32_t k,
+                            int32_t steps, int32_t* chosen);
+
 /* Per-kernel device time accumulated while options.profile_kernels = 1:
  * one record per kernel of the step sequence (update_thomas, stencil_dots,
  * dir_update), each the sum of the HIP event intervals around its launches

@@ -11,6 +11,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
@@ -66,6 +69,7 @@ struct ftgcr_handle {
 
     int nblk_col = 0, nblk_st = 0;
     int kc = 1, tx = 1, ty = 1, tz = 1, H = 4;
+    int tuned_kc = 0;   // from ftgcr_autotune (0: none)
 
     // kernel timing (options.profile_kernels)
     struct Pending {
@@ -108,6 +112,18 @@ double hill_height(const ftgcr_coeffs& c, double lon, double lat)
     return std::exp(-q * q);
 }
 
+// Autotuned levels per stencil block, per (nlon, nlat, nz, precision).
+using TuneKey = std::tuple<int, int, int, int>;
+std::mutex g_tune_mutex;
+std::map<TuneKey, int> g_tuned;
+
+int tuned_levels(const ftgcr_handle* h)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tuned.find(TuneKey{h->geo.nx, h->geo.ny, h->geo.nz, h->precision});
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
 // Levels per stencil block: as many as keep >= 1024 blocks in flight (8 at
 // most: deeper chunks raise register pressure more than they save halo).
 int auto_levels_per_block(int tx, int ty, int nz)
@@ -128,6 +144,7 @@ void set_tiling(ftgcr_handle* h)
     h->tx = (g.nx + ST_TX - 1) / ST_TX;
     h->ty = (g.ny + ST_TY - 1) / ST_TY;
     int kc = h->opt.levels_per_block;
+    if (kc != 1 && kc != 2 && kc != 4 && kc != 8 && kc != 16) kc = h->tuned_kc ? h->tuned_kc : tuned_levels(h);
     if (kc != 1 && kc != 2 && kc != 4 && kc != 8 && kc != 16) kc = auto_levels_per_block(h->tx, h->ty, g.nz);
     h->kc = kc;
     h->tz = (g.nz + kc - 1) / kc;
@@ -1005,6 +1022,63 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
     }
     HIP_TRY(hs[0], hipSetDevice(hs[0]->device));
     return solve_batch_impl(hs, n, rhs, x, tol, k, plans, stats);
+}
+
+ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_scratch_dev, int32_t k,
+                            int32_t steps, int32_t* chosen)
+{
+    if (!h) return FTGCR_E_INVALID;
+    if (!rhs_dev || !x_scratch_dev) return fail(h, FTGCR_E_INVALID, "rhs or x is NULL");
+    if (k < 1 || k > h->kmax || steps < 1) return fail(h, FTGCR_E_INVALID, "bad k or steps");
+    if (!h->ws || h->ws_bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "no workspace set");
+    HIP_TRY(h, hipSetDevice(h->device));
+    int best = tuned_levels(h);
+    if (best == 0) {
+        const ftgcr_options saved = h->opt;
+        float best_ms = 0.f;
+        const int cand[] = {2, 4, 8};
+        for (int kc : cand) {
+            if (kc > h->geo.nz) continue;
+            ftgcr_options o = saved;
+            o.levels_per_block = kc;
+            o.max_steps = steps;
+            o.profile_kernels = 0;
+            ftgcr_status rc = ftgcr_set_options(h, &o);
+            float ms_min = 0.f;
+            for (int rep = 0; rep < 2 && rc == FTGCR_OK; ++rep) {
+                HIP_TRY(h, hipMemsetAsync(x_scratch_dev, 0, (size_t)h->geo.n * sizeof(double), h->stream));
+                ftgcr_stats st;
+                std::memset(&st, 0, sizeof st);
+                rc = ftgcr_solve(h, rhs_dev, x_scratch_dev, 1e-300, k, nullptr, &st);
+                if (rc == FTGCR_OK && (rep == 0 || st.time_ms < ms_min)) ms_min = (float)st.time_ms;
+            }
+            if (rc != FTGCR_OK) {
+                ftgcr_set_options(h, &saved);
+                return rc;
+            }
+            if (best == 0 || ms_min < best_ms) {
+                best = kc;
+                best_ms = ms_min;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mutex);
+            g_tuned[TuneKey{h->geo.nx, h->geo.ny, h->geo.nz, h->precision}] = best;
+        }
+        ftgcr_status rc = ftgcr_set_options(h, &saved);
+        if (rc != FTGCR_OK) return rc;
+    }
+    h->tuned_kc = best;
+    set_tiling(h);
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+        h->graph_steps = 0;
+    }
+    ftgcr_status rc = upload_debug_inst(h);
+    if (rc != FTGCR_OK) return rc;
+    if (chosen) *chosen = h->kc;
+    return FTGCR_OK;
 }
 
 ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, int32_t cap, int32_t* n_out)

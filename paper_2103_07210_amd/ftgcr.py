@@ -27,7 +27,7 @@ LOG_CAP = 256
 EXPORTED = ["ftgcr_default_options", "ftgcr_create", "ftgcr_set_options", "ftgcr_get_options",
             "ftgcr_set_stream", "ftgcr_workspace_bytes", "ftgcr_set_workspace", "ftgcr_solve",
             "ftgcr_solve_batch", "ftgcr_destroy", "ftgcr_last_error", "ftgcr_debug_apply_A",
-            "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times"]
+            "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times", "ftgcr_autotune"]
 
 
 class FtgcrError(RuntimeError):
@@ -135,6 +135,8 @@ def load():
     lib.ftgcr_kernel_times.restype = ctypes.c_int
     lib.ftgcr_reset_kernel_times.argtypes = [H]
     lib.ftgcr_reset_kernel_times.restype = ctypes.c_int
+    lib.ftgcr_autotune.argtypes = [H, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.ftgcr_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -295,6 +297,20 @@ class Solver:
         _check(load().ftgcr_debug_apply_Pinv(self._h, ctypes.c_void_p(r_t.data_ptr()),
                                              ctypes.c_void_p(e.data_ptr())), self._h)
         return e
+
+    def autotune(self, rhs, k: int = 3, steps: int = 24) -> int:
+        """Time `steps` steps per stencil tiling on this problem and keep the
+        fastest (also for later handles of the same grid and precision).
+        Returns the chosen levels per block."""
+        import torch
+        rhs_t = self._dev(rhs)
+        scratch = torch.empty_like(rhs_t)
+        chosen = ctypes.c_int32()
+        _check(load().ftgcr_autotune(self._h, ctypes.c_void_p(rhs_t.data_ptr()),
+                                     ctypes.c_void_p(scratch.data_ptr()), int(k), int(steps),
+                                     ctypes.byref(chosen)), self._h)
+        torch.cuda.synchronize()
+        return chosen.value
 
     def kernel_times(self) -> dict:
         """{kernel name: (launches, total ms)} accumulated with profile_kernels=1."""

@@ -402,3 +402,17 @@ def test_mixed_precision_detects_r_fault(ft):
     assert st["log"][0]["step"] == 12
     assert st["status"] == ft.CONVERGED and st["rel_res_true"] <= 1e-8
     s.close()
+
+
+def test_autotune_keeps_results(ft, oracle_mod):
+    """The tiling autotuner only changes how the stencil passes are tiled:
+    after tuning, the solve still matches the oracle."""
+    _say("autotune")
+    pb = Problem(128, 64, 16, hill_amp=0.7)
+    s = ft.Solver(pb, kmax=3)
+    rhs = I.rhs(pb, 8)
+    kc = s.autotune(rhs, k=3, steps=12)
+    assert kc in (2, 4, 8)
+    assert s.options()["levels_per_block"] == 0
+    s.close()
+    _solve_parity(ft, oracle_mod, pb, 3, rhs_seed=8)
