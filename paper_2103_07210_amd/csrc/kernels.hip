@@ -617,13 +617,23 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // for both halves: the lower lane eliminates towards level 0 (near
     // coupling a_k, far coupling u_k), the upper lane towards nz-1 (near
     // u_k, far a_k).
-    constexpr int CH = H < 8 ? H : 8;
+    // FP64 streams in 4-level chunks: with 8 the half column's registers
+    // exceed 256 and the kernel drops to one wave per SIMD
+    constexpr int CHW = sizeof(T) == 8 ? 4 : 8;
+    constexpr int CH = H < CHW ? H : CHW;
     constexpr int NCH = H / CH;
+    static_assert(H % CH == 0, "chunks must tile the half column");
     T bufr[2][CH], bufa[2][CH];
     CT de[H], ga[H];
     double acc_new = 0.0, acc_st = 0.0;
     CT carry_g = 0, carry_d = 0;
     CT mm = 1, ff = 0, uu = 0;   // meeting row of the lower lane
+    CT w_near = 0;                // face below level 0 / above level nz-1
+    // r+ is stored through a pointer that walks one level per row (a fresh
+    // induction value, so the loads' 64-bit addresses need not stay live)
+    const long long wstep = upper ? -plane : plane;
+    T* rw = (mode == MODE_STEP ? rout : eout) + (long long)colc + plane * (upper ? nz - 1 : 0);
+    asm volatile("" : "+v"(rw));
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
         int k = upper ? nz - 1 - t : t;
@@ -662,12 +672,20 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
             const double rp = (double)sv;
             const CT rc = (CT)sv;
             if (mine && valid) {
-                if (mode == MODE_STEP) rout[(long long)colc + plane * k] = sv;
+                if (mode == MODE_STEP) *rw = sv;
                 acc_new = fma(v, v, acc_new);
                 acc_st = fma(rp, rp, acc_st);
             }
-            const CT wb = (k > 0) ? gz * (CT(1) + hc * s_gf[k]) : CT(0);
-            const CT wa = (k < nz - 1) ? gz * (CT(1) + hc * s_gf[k + 1]) : CT(0);
+            rw += wstep;
+            // vertical face weights of row k: the face shared with the
+            // previous row of this lane was computed there (w_near); the far
+            // face (k + 1 for the lower lane, k for the upper one) is new
+            const int f = upper ? k : k + 1;
+            const CT gff = s_gf[f];
+            const CT w_far = (f > 0 && f < nz) ? gz * (CT(1) + hc * gff) : CT(0);
+            const CT wb = upper ? w_far : w_near;
+            const CT wa = upper ? w_near : w_far;
+            w_near = w_far;
             const CT diag = opsig_c * (((h0 + s_gc[k] * h1) + wb) + wa);
             const CT near = upper ? -wa : -wb;
             const CT far = upper ? -wb : -wa;
@@ -700,12 +718,18 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     CT xv = upper ? xl : xm;
     if (valid && !upper) eout[(long long)colc + plane * (h - 1)] = (T)xm;
     const int nback = upper ? nup : h - 1;
+    // the store address walks one level per row from a fresh base: were it
+    // recomputed from the forward sweep's expressions, the compiler would
+    // keep all of the half column's 64-bit addresses live across the sweep
+    const long long estep = upper ? plane : -plane;
+    T* ep = eout + (long long)colc + plane * (upper ? h : h - 2);
+    asm volatile("" : "+v"(ep));
 #pragma unroll
     for (int q = H - 1; q >= 0; --q) {
         if (q < nback) {
             xv = de[q] - ga[q] * xv;
-            const int k = upper ? nz - 1 - q : q;
-            if (valid) eout[(long long)colc + plane * k] = (T)xv;
+            if (valid) *ep = (T)xv;
+            ep += estep;
         }
     }
     if (mode == MODE_DEBUG) return;
