@@ -45,6 +45,30 @@ __device__ __forceinline__ int find_inst(const int* blk0, int n, int b)
     return lo;
 }
 
+// Pointers that pass through LDS (per-block tables of the direction
+// vectors) or through an empty asm statement come back as generic pointers,
+// and accesses through them compile to flat instructions, which count
+// against both the memory and the LDS counters: every LDS access and wave
+// shuffle after them would wait for all outstanding HBM traffic.  The
+// vectors are in global memory; these views say so.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+using gptr_mut = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T* p)
+{
+    return (gptr<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ gptr_mut<T> as_global_mut(T* p)
+{
+    return (gptr_mut<T>)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -67,15 +91,16 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 // (value-major: a value's partials are contiguous), by one RED_THREADS block:
 // thread t adds blocks t, t + RED_THREADS, ... in order, then the waves are
 // summed in a fixed order.  Every value's loads are independent, so each
-// pass over the blocks is one round trip for all values.  out[q] is valid in
-// every thread.
+// pass over the blocks is one round trip for all values.  The returned LDS
+// array holds the nv sums; out, if not null, gets the first two of them in
+// registers.  Both are valid in every thread.
 template <typename T>
-__device__ __forceinline__ void sum_partials(const Inst<T>& in, int nblk, int nv, double* out)
+__device__ __forceinline__ const double* sum_partials(const Inst<T>& in, int nblk, int nv, double* out)
 {
     constexpr int NW = RED_THREADS / 64;
     __shared__ double sh[NV_MAX][NW];
     __shared__ double res[NV_MAX];
-    const double* part = in.part;
+    const gptr<double> part = as_global(in.part);
     const long long stride = in.pstride;
     double acc[NV_MAX];
 #pragma unroll
@@ -101,7 +126,9 @@ __device__ __forceinline__ void sum_partials(const Inst<T>& in, int nblk, int nv
         res[threadIdx.x] = t;
     }
     __syncthreads();
-    for (int q = 0; q < nv; ++q) out[q] = res[q];
+    if (out != nullptr)
+        for (int q = 0; q < 2 && q < nv; ++q) out[q] = res[q];
+    return res;
 }
 
 // Per-column constants: hill_amp * h at the five horizontal positions and
@@ -127,90 +154,190 @@ __device__ __forceinline__ ColW col_weights(const Geo& g, int i, int j)
     return c;
 }
 
-// Face weights W = c_face * metric of cell (i, j, k) and the diagonal
-// (1 + sigma) * sum(W).  Zero-flux faces (poles, bottom, top) are exactly 0.
-struct LevW {
-    double w, e, s, n, b, a, diag;
+// Per-column constants of a row of A.  A horizontal face weight is
+// G * (1 + h * g_k) (metric G, hill term h, vertical decay g_k at the cell's
+// level), so the horizontal part of a row splits into a level-independent
+// sum and a second one scaled by g_k:
+//   sum_f W_f x_f = (Gx (x_w + x_e) + Gy_s x_s + Gy_n x_n)
+//                 + g_k (Gx h_w x_w + Gx h_e x_e + Gy_s h_s x_s + Gy_n h_n x_n)
+// and the horizontal part of the diagonal is h0 + g_k h1.  The column solve
+// forms the same diagonal from the same constants, so P's diagonal is A's
+// bit for bit.
+struct RowC {
+    double gx, gys, gyn;     // face metrics
+    double cw, ce, cs, cn;   // metric * hill term of the four side faces
+    double h0, h1;           // horizontal diagonal = h0 + g_k h1
+    double gz, hc;           // vertical face weight = gz (1 + hc g_face)
 };
 
-// gc / gf: the vertical decay at centres and faces (global memory, or a
-// copy in LDS where per-level global loads would wait behind stores).
-__device__ __forceinline__ LevW level_weights(const ColW& c, const double* gc, const double* gf, int nz,
-                                              double opsig, int k)
+__device__ __forceinline__ RowC row_consts(const ColW& c)
 {
-    LevW L;
-    const double gk = gc[k];
-    L.w = c.gx * (1.0 + c.hw * gk);
-    L.e = c.gx * (1.0 + c.he * gk);
-    L.s = c.gys * (1.0 + c.hs * gk);
-    L.n = c.gyn * (1.0 + c.hn * gk);
-    L.b = (k > 0) ? c.gz * (1.0 + c.hc * gf[k]) : 0.0;
-    L.a = (k < nz - 1) ? c.gz * (1.0 + c.hc * gf[k + 1]) : 0.0;
-    const double d0 = ((((L.w + L.e) + L.s) + L.n) + L.b) + L.a;
-    L.diag = opsig * d0;
-    return L;
+    RowC r;
+    r.gx = c.gx;
+    r.gys = c.gys;
+    r.gyn = c.gyn;
+    r.cw = c.gx * c.hw;
+    r.ce = c.gx * c.he;
+    r.cs = c.gys * c.hs;
+    r.cn = c.gyn * c.hn;
+    r.h0 = ((c.gx + c.gx) + c.gys) + c.gyn;
+    r.h1 = ((c.gx * (c.hw + c.he) + c.gys * c.hs) + c.gyn * c.hn);
+    r.gz = c.gz;
+    r.hc = c.hc;
+    return r;
 }
 
-__device__ __forceinline__ LevW level_weights(const ColW& c, const Geo& g, int k)
+// Vertical face weight of face f (between levels f-1 and f); 0 at the
+// bottom (f = 0) and top (f = nz) faces.
+__device__ __forceinline__ double vface(const RowC& r, double gf, int f, int nz)
 {
-    return level_weights(c, g.gc, g.gf, g.nz, g.opsig, k);
+    return (f > 0 && f < nz) ? r.gz * fma(r.hc, gf, 1.0) : 0.0;
 }
 
-__device__ __forceinline__ double apply_row(const LevW& L, double xc, double xw, double xe,
-                                            double xs, double xn, double xb, double xa)
+// Wavefront shifts by one lane (DPP): lane l receives lane l-1's value
+// (shift_up) or lane l+1's (shift_down); lanes with no source get 0.  Every
+// lane of the wavefront must be active.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_up)
 {
-    double off = L.w * xw;
-    off = fma(L.e, xe, off);
-    off = fma(L.s, xs, off);
-    off = fma(L.n, xn, off);
-    off = fma(L.b, xb, off);
-    off = fma(L.a, xa, off);
-    return fma(L.diag, xc, -off);
+    const long long b = __double_as_longlong(v);
+    int lo, hi;
+    if (ctrl_up) {
+        lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xF, 0xF, false);        // wave_shr:1
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xF, 0xF, false);        // wave_shl:1
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// (A x) at levels k0 .. k0+KC-1 of column (i, j) (i, j in range, k0 < nz).
-// Branch-free: every load uses a clamped in-range address and is issued up
-// front; missing neighbours (beyond the poles, bottom, top) are then
-// selected to 0 (a select, not a product, so a NaN at the clamped address
-// cannot leak) and carry weight 0.  Entries at levels >= nz are garbage and
-// must be masked by the caller.
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// (A x) at levels k0 .. k0+KC-1 of column (i, j) (i, j clamped in range,
+// k0 < nz), for a whole block: a block is a 64 x 4 tile of columns, one
+// wavefront per row (lane = i - tile start), so most neighbours are values
+// other lanes already loaded:
+//   west / east  the adjacent lanes' centre values, moved by DPP; the row
+//                segment's two edge values (one of them the periodic wrap)
+//                come from one load instruction, lanes 0..KC-1 west and
+//                32..32+KC-1 east, broadcast by readlane;
+//   south/north  the adjacent rows' centre values through LDS; only the
+//                tile's first and last rows load a halo row;
+//   below/above  registers (each thread holds its KC levels and one more on
+//                either side).
+// All loads use clamped in-range addresses and are issued before the first
+// is used; missing neighbours (beyond the poles, bottom, top) are selected
+// to 0 (a select, not a product, so a NaN at a clamped address cannot leak)
+// and carry weight 0.  Entries at levels >= nz or in clamped columns are
+// garbage and must be masked by the caller.  Every thread of the block must
+// call this (it holds a barrier).
 template <typename TI, int KC>
 __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict__ x, int i, int j,
                                               int k0, double (&out)[KC])
 {
-    const ColW c = col_weights(g, i, j);
-    const int nz = g.nz;
+    static_assert(ST_TX == 64 && ST_TY * ST_TX == ST_THREADS, "one wavefront per tile row");
+    static_assert(KC <= 32, "edge lanes");
+    __shared__ double s_row[ST_TY][KC][ST_TX];
+    const RowC rc = row_consts(col_weights(g, i, j));
+    const int nz = g.nz, nx = g.nx;
     const long long plane = (long long)g.ncols;
-    const int iw = (i == 0) ? g.nx - 1 : i - 1;
-    const int ie = (i == g.nx - 1) ? 0 : i + 1;
+    const int lane = threadIdx.x & (ST_TX - 1);
+    const int w = threadIdx.x / ST_TX;
+    // tile start (lane 0 is never a clamped column) and the last real lane
+    const int i0 = __builtin_amdgcn_readlane(i, 0);
+    const int last = (nx - 1 - i0 < ST_TX - 1) ? nx - 1 - i0 : ST_TX - 1;
+    const int iw0 = (i0 == 0) ? nx - 1 : i0 - 1;
+    const int ie0 = (i0 + last + 1 == nx) ? 0 : i0 + last + 1;
     const bool has_s = j > 0, has_n = j < g.ny - 1;
-    const long long row = (long long)j * g.nx;
-    const long long so = has_s ? -(long long)g.nx : 0;
-    const long long no = has_n ? (long long)g.nx : 0;
-    double xv[KC + 2], xw[KC], xe[KC], xs[KC], xn[KC];
+    const long long row = (long long)j * nx;
+    double xv[KC + 2], xs[KC], xn[KC];
 #pragma unroll
     for (int t = 0; t < KC + 2; ++t) {
         int k = k0 - 1 + t;
         k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
         xv[t] = (double)x[row + i + plane * k];
     }
+    double edge;
+    {
+        const int t = lane < 32 ? lane : lane - 32;
+        int k = k0 + (t < KC ? t : KC - 1);
+        k = k > nz - 1 ? nz - 1 : k;
+        edge = (double)x[row + plane * k + (lane < 32 ? iw0 : ie0)];
+    }
+    // halo rows of the tile (first row: south, last row: north)
+    if (w == 0) {
+        const long long so = has_s ? -(long long)nx : 0;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+            xs[kk] = (double)x[row + so + plane * k + i];
+        }
+    }
+    if (w == ST_TY - 1) {
+        const long long no = has_n ? (long long)nx : 0;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+            xn[kk] = (double)x[row + no + plane * k + i];
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) s_row[w][kk][lane] = xv[kk + 1];
+    __syncthreads();
+    if (w > 0) {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) xs[kk] = s_row[w - 1][kk][lane];
+    }
+    if (w < ST_TY - 1) {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) xn[kk] = s_row[w + 1][kk][lane];
+    }
+    double xw[KC], xe[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-        const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
-        const long long o = row + plane * k;
-        xw[kk] = (double)x[o + iw];
-        xe[kk] = (double)x[o + ie];
-        xs[kk] = (double)x[o + i + so];
-        xn[kk] = (double)x[o + i + no];
+        const double up = dpp_f64(xv[kk + 1], 1);
+        const double dn = dpp_f64(xv[kk + 1], 0);
+        const double we = readlane_f64(edge, kk);
+        const double ee = readlane_f64(edge, 32 + kk);
+        xw[kk] = (lane == 0) ? we : up;
+        xe[kk] = (lane == last) ? ee : dn;
+    }
+    // vertical face weights of faces k0 .. k0+KC (level k has faces k, k+1)
+    double wf[KC + 1];
+#pragma unroll
+    for (int t = 0; t <= KC; ++t) {
+        const int f = k0 + t;
+        const int fq = f > nz ? nz : f;
+        wf[t] = vface(rc, g.gf[fq], f, nz);
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
         const int kq = (k > nz - 1) ? nz - 1 : k;
-        const LevW L = level_weights(c, g, kq);
+        const double gk = g.gc[kq];
+        const double wb = wf[kk], wa = wf[kk + 1];
+        const double xsv = has_s ? xs[kk] : 0.0;
+        const double xnv = has_n ? xn[kk] : 0.0;
         const double xb = (k > 0) ? xv[kk] : 0.0;
         const double xa = (k + 1 < nz) ? xv[kk + 2] : 0.0;
-        out[kk] = apply_row(L, xv[kk + 1], xw[kk], xe[kk], has_s ? xs[kk] : 0.0, has_n ? xn[kk] : 0.0, xb, xa);
+        double t1 = rc.gx * (xw[kk] + xe[kk]);
+        t1 = fma(rc.gys, xsv, t1);
+        t1 = fma(rc.gyn, xnv, t1);
+        double t2 = rc.cw * xw[kk];
+        t2 = fma(rc.ce, xe[kk], t2);
+        t2 = fma(rc.cs, xsv, t2);
+        t2 = fma(rc.cn, xnv, t2);
+        double off = fma(gk, t2, t1);
+        off = fma(wb, xb, off);
+        off = fma(wa, xa, off);
+        const double diag = g.opsig * ((fma(gk, rc.h1, rc.h0) + wb) + wa);
+        out[kk] = fma(diag, xv[kk + 1], -off);
     }
 }
 
@@ -601,12 +728,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const int nup = nz - h;        // upper half: levels [h, nz)
     const int nmine = upper ? nup : h;
     const ColW c = col_weights(g, i, j);
-    // horizontal part of the diagonal: sum of the four side weights is
-    // h0 + g_k h1 with per-column constants (fewer operations per level than
-    // forming the four weights; equal up to rounding)
-    const CT h0 = (CT)(((c.gx + c.gx) + c.gys) + c.gyn);
-    const CT h1 = (CT)((c.gx * (c.hw + c.he) + c.gys * c.hs) + c.gyn * c.hn);
-    const CT gz = (CT)c.gz, hc = (CT)c.hc;
+    // diagonal h0 + g_k h1 + vertical faces, from the same per-column
+    // constants and in the same order as the stencil rows (identical in FP64)
+    const RowC rcst = row_consts(c);
+    const CT h0 = (CT)rcst.h0;
+    const CT h1 = (CT)rcst.h1;
+    const CT gz = (CT)rcst.gz, hc = (CT)rcst.hc;
 
     // The half column streams in chunks of CH levels, each chunk's loads
     // issued one chunk ahead of its elimination (a two-stage software
@@ -632,7 +759,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // r+ is stored through a pointer that walks one level per row (a fresh
     // induction value, so the loads' 64-bit addresses need not stay live)
     const long long wstep = upper ? -plane : plane;
-    T* rw = (mode == MODE_STEP ? rout : eout) + (long long)colc + plane * (upper ? nz - 1 : 0);
+    gptr_mut<T> rw = as_global_mut(mode == MODE_STEP ? rout : eout) + (long long)colc + plane * (upper ? nz - 1 : 0);
     asm volatile("" : "+v"(rw));
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
@@ -682,11 +809,11 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
             // face (k + 1 for the lower lane, k for the upper one) is new
             const int f = upper ? k : k + 1;
             const CT gff = s_gf[f];
-            const CT w_far = (f > 0 && f < nz) ? gz * (CT(1) + hc * gff) : CT(0);
+            const CT w_far = (f > 0 && f < nz) ? gz * fma(hc, gff, CT(1)) : CT(0);
             const CT wb = upper ? w_far : w_near;
             const CT wa = upper ? w_near : w_far;
             w_near = w_far;
-            const CT diag = opsig_c * (((h0 + s_gc[k] * h1) + wb) + wa);
+            const CT diag = opsig_c * ((fma(s_gc[k], h1, h0) + wb) + wa);
             const CT near = upper ? -wa : -wb;
             const CT far = upper ? -wb : -wa;
             const CT mk = (q == 0) ? diag : diag - near * carry_g;
@@ -722,7 +849,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // recomputed from the forward sweep's expressions, the compiler would
     // keep all of the half column's 64-bit addresses live across the sweep
     const long long estep = upper ? plane : -plane;
-    T* ep = eout + (long long)colc + plane * (upper ? h : h - 2);
+    gptr_mut<T> ep = as_global_mut(eout) + (long long)colc + plane * (upper ? h : h - 2);
     asm volatile("" : "+v"(ep));
 #pragma unroll
     for (int q = H - 1; q >= 0; --q) {
@@ -788,7 +915,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
     for (int l = 0; l <= KMAX; ++l) {
         acc[l] = 0.0;
         if (l <= nu) {
-            const T* apl = s_ap[l];
+            const gptr<T> apl = as_global(s_ap[l]);
             double av[KC];
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
@@ -824,10 +951,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(Table<T> tb)
     SolveState* st = in.st;
     if (st->status != RUNNING || !st->active) return;
     const int nu = st->nu;
-    double v[NV_MAX];
-    sum_partials(in, in.nblk_st, nu + 1, v);
-    if (threadIdx.x == 0)
-        for (int l = 0; l <= nu; ++l) st->alpha[l] = -v[l] / st->d[l];
+    const double* v = sum_partials(in, in.nblk_st, nu + 1, nullptr);
+    if ((int)threadIdx.x <= nu) st->alpha[threadIdx.x] = -v[threadIdx.x] / st->d[threadIdx.x];
     if (threadIdx.x == 0) st->x_dst = (st->x_base == st->x_bak) ? 1 - st->x_base : st->x_base;
 }
 
@@ -883,8 +1008,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
 #pragma unroll
     for (int l = 0; l < KMAX; ++l) {
         if (l <= nu) {
-            const T* pl = s_p[l];
-            const T* apl = s_ap[l];
+            const gptr<T> pl = as_global(s_p[l]);
+            const gptr<T> apl = as_global(s_ap[l]);
             const double al = s_al[l];
             const double bl = s_be[l];
             double pv[KC], av[KC];
@@ -1120,12 +1245,11 @@ __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, 
 {
     const Inst<double>& in = tb.inst[0];
     const StPos ps = st_pos(in, blockIdx.x);
-    if (!ps.col_ok) return;
     double ax[KC];
     stencil_chunk<double, KC>(in.g, x, ps.i, ps.j, ps.k0, ax);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
-        if (ps.k0 + kk < in.g.nz)
+        if (ps.col_ok && ps.k0 + kk < in.g.nz)
             y[(long long)ps.i + (long long)in.g.nx * ps.j + (long long)in.g.ncols * (ps.k0 + kk)] = ax[kk];
 }
 
