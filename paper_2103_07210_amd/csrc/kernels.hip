@@ -69,11 +69,37 @@ __device__ __forceinline__ gptr_mut<T> as_global_mut(T* p)
     return (gptr_mut<T>)p;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes as a pairwise tree in lane order,
+// ((v0 + v1) + (v2 + v3)) + ..., bitwise equal in every lane: DPP moves
+// pair lanes l ^ 1 and l ^ 2 (quad permutes), then quads and half rows
+// (half-row and row mirrors: every lane of a quad, then of a half row,
+// holds the same value, so a mirror pairs the right partial sums; a + b and
+// b + a round alike); the four row sums are read by readlane.  No LDS
+// traffic.  Every lane must be active.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp_mov_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov_f64<0x141>(v);   // row_half_mirror
+    v += dpp_mov_f64<0x140>(v);   // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // Sum over a 256-thread block; every thread gets the result.
@@ -208,14 +234,6 @@ __device__ __forceinline__ double dpp_f64(double v, int ctrl_up)
         lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xF, 0xF, false);        // wave_shl:1
         hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
     }
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
