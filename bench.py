@@ -97,7 +97,7 @@ def main():
 
     s64 = ftgcr.Solver(pb, "fp64", kmax=K, poll_steps=32)
     kc64 = s64.autotune(rhs, k=K, steps=24) if not args.profile_run else s64.options()["levels_per_block"]
-    print(f"[bench] fp64 stencil tiling: {kc64} levels per block", flush=True)
+    print(f"[bench] fp64 stencil tiling: {kc64 or 'automatic'} levels per block", flush=True)
     for _ in range(args.warmup):
         x.zero_()
         s64.solve(rhs, x, tol=TOL, k=K)
