@@ -78,7 +78,7 @@ __device__ __forceinline__ double dpp_mov_f64(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l)
+__device__ __forceinline__ double lane_read(double v, int l)
 {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)b, l);
@@ -99,7 +99,7 @@ __device__ __forceinline__ double wave_sum(double v)
     v += dpp_mov_f64<0x4E>(v);    // quad_perm [2,3,0,1]
     v += dpp_mov_f64<0x141>(v);   // row_half_mirror
     v += dpp_mov_f64<0x140>(v);   // row_mirror
-    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // Sum over a 256-thread block; every thread gets the result.
@@ -220,10 +220,40 @@ __device__ __forceinline__ double vface(const RowC& r, double gf, int f, int nz)
     return (f > 0 && f < nz) ? r.gz * fma(r.hc, gf, 1.0) : 0.0;
 }
 
+// The same constants rounded to binary32, for the stencil of the mixed
+// form (binary32 vectors): there L(e) is stored in binary32, so forming it
+// in binary32 arithmetic changes it by the order of that rounding, at half
+// the vector-ALU cost of FP64.
+struct RowCf {
+    float gx, gys, gyn, cw, ce, cs, cn, h0, h1, gz, hc;
+};
+
+template <typename AT>
+struct RowOf;
+template <>
+struct RowOf<double> {
+    using type = RowC;
+    __device__ static RowC make(const RowC& r) { return r; }
+};
+template <>
+struct RowOf<float> {
+    using type = RowCf;
+    __device__ static RowCf make(const RowC& r)
+    {
+        return RowCf{(float)r.gx, (float)r.gys, (float)r.gyn, (float)r.cw, (float)r.ce, (float)r.cs,
+                     (float)r.cn, (float)r.h0, (float)r.h1, (float)r.gz, (float)r.hc};
+    }
+};
+
+__device__ __forceinline__ float vface(const RowCf& r, float gf, int f, int nz)
+{
+    return (f > 0 && f < nz) ? r.gz * fmaf(r.hc, gf, 1.0f) : 0.0f;
+}
+
 // Wavefront shifts by one lane (DPP): lane l receives lane l-1's value
 // (shift_up) or lane l+1's (shift_down); lanes with no source get 0.  Every
 // lane of the wavefront must be active.
-__device__ __forceinline__ double dpp_f64(double v, int ctrl_up)
+__device__ __forceinline__ double lane_shift(double v, int ctrl_up)
 {
     const long long b = __double_as_longlong(v);
     int lo, hi;
@@ -235,6 +265,19 @@ __device__ __forceinline__ double dpp_f64(double v, int ctrl_up)
         hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
     }
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float lane_shift(float v, int ctrl_up)
+{
+    const int b = __float_as_int(v);
+    const int r = ctrl_up ? __builtin_amdgcn_update_dpp(0, b, 0x138, 0xF, 0xF, false)
+                          : __builtin_amdgcn_update_dpp(0, b, 0x130, 0xF, 0xF, false);
+    return __int_as_float(r);
+}
+
+__device__ __forceinline__ float lane_read(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // (A x) at levels k0 .. k0+KC-1 of column (i, j) (i, j clamped in range,
@@ -261,8 +304,9 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
 {
     static_assert(ST_TX == 64 && ST_TY * ST_TX == ST_THREADS, "one wavefront per tile row");
     static_assert(KC <= 32, "edge lanes");
-    __shared__ double s_row[ST_TY][KC][ST_TX];
-    const RowC rc = row_consts(col_weights(g, i, j));
+    using AT = TI;   // arithmetic type: FP64 for FP64 vectors, binary32 for binary32
+    __shared__ AT s_row[ST_TY][KC][ST_TX];
+    const typename RowOf<AT>::type rc = RowOf<AT>::make(row_consts(col_weights(g, i, j)));
     const int nz = g.nz, nx = g.nx;
     const long long plane = (long long)g.ncols;
     const int lane = threadIdx.x & (ST_TX - 1);
@@ -274,19 +318,19 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
     const int ie0 = (i0 + last + 1 == nx) ? 0 : i0 + last + 1;
     const bool has_s = j > 0, has_n = j < g.ny - 1;
     const long long row = (long long)j * nx;
-    double xv[KC + 2], xs[KC], xn[KC];
+    AT xv[KC + 2], xs[KC], xn[KC];
 #pragma unroll
     for (int t = 0; t < KC + 2; ++t) {
         int k = k0 - 1 + t;
         k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
-        xv[t] = (double)x[row + i + plane * k];
+        xv[t] = (AT)x[row + i + plane * k];
     }
-    double edge;
+    AT edge;
     {
         const int t = lane < 32 ? lane : lane - 32;
         int k = k0 + (t < KC ? t : KC - 1);
         k = k > nz - 1 ? nz - 1 : k;
-        edge = (double)x[row + plane * k + (lane < 32 ? iw0 : ie0)];
+        edge = (AT)x[row + plane * k + (lane < 32 ? iw0 : ie0)];
     }
     // halo rows of the tile (first row: south, last row: north)
     if (w == 0) {
@@ -294,7 +338,7 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
-            xs[kk] = (double)x[row + so + plane * k + i];
+            xs[kk] = (AT)x[row + so + plane * k + i];
         }
     }
     if (w == ST_TY - 1) {
@@ -302,7 +346,7 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
-            xn[kk] = (double)x[row + no + plane * k + i];
+            xn[kk] = (AT)x[row + no + plane * k + i];
         }
     }
 #pragma unroll
@@ -316,46 +360,48 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) xn[kk] = s_row[w + 1][kk][lane];
     }
-    double xw[KC], xe[KC];
+    AT xw[KC], xe[KC];
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-        const double up = dpp_f64(xv[kk + 1], 1);
-        const double dn = dpp_f64(xv[kk + 1], 0);
-        const double we = readlane_f64(edge, kk);
-        const double ee = readlane_f64(edge, 32 + kk);
+        const AT up = lane_shift(xv[kk + 1], 1);
+        const AT dn = lane_shift(xv[kk + 1], 0);
+        const AT we = lane_read(edge, kk);
+        const AT ee = lane_read(edge, 32 + kk);
         xw[kk] = (lane == 0) ? we : up;
         xe[kk] = (lane == last) ? ee : dn;
     }
     // vertical face weights of faces k0 .. k0+KC (level k has faces k, k+1)
-    double wf[KC + 1];
+    AT wf[KC + 1];
 #pragma unroll
     for (int t = 0; t <= KC; ++t) {
         const int f = k0 + t;
         const int fq = f > nz ? nz : f;
-        wf[t] = vface(rc, g.gf[fq], f, nz);
+        wf[t] = vface(rc, (AT)g.gf[fq], f, nz);
     }
+    const AT opsig = (AT)g.opsig;
+    const AT zero = AT(0);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
         const int kq = (k > nz - 1) ? nz - 1 : k;
-        const double gk = g.gc[kq];
-        const double wb = wf[kk], wa = wf[kk + 1];
-        const double xsv = has_s ? xs[kk] : 0.0;
-        const double xnv = has_n ? xn[kk] : 0.0;
-        const double xb = (k > 0) ? xv[kk] : 0.0;
-        const double xa = (k + 1 < nz) ? xv[kk + 2] : 0.0;
-        double t1 = rc.gx * (xw[kk] + xe[kk]);
+        const AT gk = (AT)g.gc[kq];
+        const AT wb = wf[kk], wa = wf[kk + 1];
+        const AT xsv = has_s ? xs[kk] : zero;
+        const AT xnv = has_n ? xn[kk] : zero;
+        const AT xb = (k > 0) ? xv[kk] : zero;
+        const AT xa = (k + 1 < nz) ? xv[kk + 2] : zero;
+        AT t1 = rc.gx * (xw[kk] + xe[kk]);
         t1 = fma(rc.gys, xsv, t1);
         t1 = fma(rc.gyn, xnv, t1);
-        double t2 = rc.cw * xw[kk];
+        AT t2 = rc.cw * xw[kk];
         t2 = fma(rc.ce, xe[kk], t2);
         t2 = fma(rc.cs, xsv, t2);
         t2 = fma(rc.cn, xnv, t2);
-        double off = fma(gk, t2, t1);
+        AT off = fma(gk, t2, t1);
         off = fma(wb, xb, off);
         off = fma(wa, xa, off);
-        const double diag = g.opsig * ((fma(gk, rc.h1, rc.h0) + wb) + wa);
-        out[kk] = fma(diag, xv[kk + 1], -off);
+        const AT diag = opsig * ((fma(gk, rc.h1, rc.h0) + wb) + wa);
+        out[kk] = (double)fma(diag, xv[kk + 1], -off);
     }
 }
 
