@@ -87,8 +87,11 @@ typedef struct {
     int64_t hist_cap;        /* entries of the per-step residual history kept   */
     int32_t use_graphs;      /* 1: replay captured step sequences (hipGraph)     */
     int32_t levels_per_block;/* stencil kernels: levels per block (0 = auto)    */
-    int32_t profile_kernels; /* 1: time every step kernel with a HIP event pair
-                                on the solve stream (ftgcr_kernel_times)         */
+    int32_t profile_kernels; /* time step kernels with a HIP event pair each on
+                                the solve stream (ftgcr_kernel_times): 0 off,
+                                1 all three, else a mask of bit 1
+                                update_thomas, bit 2 stencil_dots, bit 3
+                                dir_update                                      */
     int32_t pad_;
 } ftgcr_options;
 
@@ -213,7 +216,7 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n,
 ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_scratch_dev, int32_t k,
                             int32_t steps, int32_t* chosen);
 
-/* Per-kernel device time accumulated while options.profile_kernels = 1:
+/* Per-kernel device time accumulated while options.profile_kernels != 0:
  * one record per kernel of the step sequence (update_thomas, stencil_dots,
  * dir_update), each the sum of the HIP event intervals around its launches
  * (launches enqueued after the solve ended are not counted).  Writes min(cap, count) records

@@ -330,7 +330,11 @@ struct Runner {
     template <class F>
     void timed(int cls, F&& launch)
     {
-        if (!h->opt.profile_kernels) {
+        // profile_kernels: 1 times all three step kernels; any other nonzero
+        // value is a mask (bit 1 update_thomas, bit 2 stencil_dots, bit 3
+        // dir_update)
+        const int mask = h->opt.profile_kernels == 1 ? 0xE : h->opt.profile_kernels;
+        if (!(mask & (2 << cls))) {
             launch();
             return;
         }

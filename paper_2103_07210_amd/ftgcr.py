@@ -313,7 +313,7 @@ class Solver:
         return chosen.value
 
     def kernel_times(self) -> dict:
-        """{kernel name: (launches, total ms)} accumulated with profile_kernels=1."""
+        """{kernel name: (launches, total ms)} accumulated while profile_kernels is on."""
         buf = (KernelTime * 16)()
         n = ctypes.c_int32()
         _check(load().ftgcr_kernel_times(self._h, buf, 16, ctypes.byref(n)), self._h)
