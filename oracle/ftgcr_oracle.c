@@ -236,7 +236,7 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
     const int64_t n = (int64_t)pb->nx * pb->ny * pb->nz;
     for (int32_t q = 0; q < n_events; ++q) {
         const orc_event* ev = &events[q];
-        if (ev->vec < ORC_V_X || ev->vec > ORC_V_AP || ev->count < 0) return -1;
+        if (ev->vec < ORC_V_X || ev->vec > ORC_V_E || ev->count < 0) return -1;
         for (int64_t t = 0; t < ev->count; ++t) {
             int64_t at = ev->idx ? ev->idx[t] : ev->start + t;
             int bit = ev->bits ? (int)ev->bits[t] : (int)ev->bit;
@@ -306,7 +306,7 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
 
             /* S1: harness-planned bit flips, before anything reads this step. */
             for (int32_t q = 0; q < n_events; ++q) {
-                if (events[q].step != s) continue;
+                if (events[q].step != s || events[q].vec == ORC_V_E) continue;
                 double* target = events[q].vec == ORC_V_X ? x
                                : events[q].vec == ORC_V_R ? r
                                : events[q].vec == ORC_V_P ? p_nu : ap_nu;
@@ -371,8 +371,16 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
             accepted += 1;
             rr_old = rr_new;
 
-            /* S5: e = P^{-1} r, L(e), alpha_l = -<L(e), Lp^l> / <Lp^l, Lp^l>. */
+            /* S5: e = P^{-1} r, L(e), alpha_l = -<L(e), Lp^l> / <Lp^l, Lp^l>.
+             * Planned flips of the preconditioner output (the paper's injection
+             * site, Section 3) land on e before anything reads it. */
             orc_apply_pinv(pb, wx, wy, wz, r, e);
+            for (int32_t q = 0; q < n_events; ++q) {
+                if (events[q].step != s || events[q].vec != ORC_V_E) continue;
+                apply_event(&events[q], e);
+                st->events_applied += 1;
+                events_since_rb = 1;
+            }
             orc_apply_A(pb, wx, wy, wz, e, le);
             for (int l = 0; l <= nu; ++l)
                 alpha[l] = -orc_dot(n, le, apv + (int64_t)l * n) / d[l];

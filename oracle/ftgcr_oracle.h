@@ -70,10 +70,15 @@ void orc_apply_pinv(const orc_problem* pb, const double* wx, const double* wy,
 double orc_dot(int64_t n, const double* a, const double* b);
 
 /* One fault event: XOR bit(s) into the IEEE-754 binary64 pattern of entries of
- * one working vector at the start of executed step `step` (1-based), before
- * that step reads anything.  idx == NULL means the contiguous range
- * [start, start+count).  bits == NULL means every entry gets bit `bit`. */
-enum { ORC_V_X = 0, ORC_V_R = 1, ORC_V_P = 2, ORC_V_AP = 3 };
+ * one working vector during executed step `step` (1-based).  X, R, P, AP: the
+ * iterate, the residual, the current direction or its image, at the start of
+ * the step before it reads anything.  E: the preconditioner output
+ * e = P^{-1}(r) of the step, right after it is computed and before L(e) and
+ * the new direction read it (the paper's injection site, Section 3); a step
+ * that exits or rolls back never computes e, so its E events do not apply.
+ * idx == NULL means the contiguous range [start, start+count).  bits == NULL
+ * means every entry gets bit `bit`. */
+enum { ORC_V_X = 0, ORC_V_R = 1, ORC_V_P = 2, ORC_V_AP = 3, ORC_V_E = 4 };
 typedef struct {
     int64_t step;
     int32_t vec;

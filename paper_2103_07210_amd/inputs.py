@@ -21,8 +21,8 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-VEC_X, VEC_R, VEC_P, VEC_AP = 0, 1, 2, 3
-VEC_NAMES = {"x": VEC_X, "r": VEC_R, "p": VEC_P, "ap": VEC_AP}
+VEC_X, VEC_R, VEC_P, VEC_AP, VEC_E = 0, 1, 2, 3, 4
+VEC_NAMES = {"x": VEC_X, "r": VEC_R, "p": VEC_P, "ap": VEC_AP, "e": VEC_E}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -55,9 +55,11 @@ class Problem:
 
 @dataclasses.dataclass
 class FaultEvent:
-    """XOR `bit` (or per-entry `bits`) into entries of one working vector at
-    the start of executed step `step` (1-based).  `idx` lists flat canonical
-    indices; if it is None the entries are the range [start, start+count)."""
+    """XOR `bit` (or per-entry `bits`) into entries of one working vector
+    during executed step `step` (1-based): x, r, p^nu, L(p^nu) at the start
+    of the step; e = P^-1(r) right after the step's preconditioner (only if
+    the step passes its tests).  `idx` lists flat canonical indices; if it
+    is None the entries are the range [start, start+count)."""
     step: int
     vec: int
     bit: int = 62
@@ -93,7 +95,7 @@ C4_SIZES = ((64, 32, 8), (128, 64, 16), (192, 96, 24), (256, 128, 32))
 
 SEEDS = {"c1_rhs": 1, "c1_plan": 101, "c2_rhs": 2, "c2_plan0": 1000,
          "c3_rhs": 3, "c4_table": 4, "c4_rhs0": 4000, "c4_plan0": 4100,
-         "c5_rhs": 5, "c5_plan": 501}
+         "c5_rhs": 5, "c5_plan": 501, "paper_plan0": 6000}
 
 
 def rhs(problem: Problem, seed: int) -> np.ndarray:
@@ -143,6 +145,44 @@ def block_plan(problem: Problem, step: int = 10, vec: str = "r", fraction: float
     cnt = int(math.ceil(fraction * problem.n))
     return [FaultEvent(step=step, vec=vec, bit=bit,
                        start=int(rng.integers(0, problem.n - cnt + 1)), count=cnt)]
+
+
+def process_entries(problem: Problem, procs: int, rank: int) -> np.ndarray:
+    """Canonical indices of the entries one of `procs` processes would own
+    under a horizontal decomposition into bands of whole columns (column
+    index j * nx + i split into `procs` contiguous ranges, all levels)."""
+    ncols = problem.nx * problem.ny
+    lo = (ncols * rank) // procs
+    hi = (ncols * (rank + 1)) // procs
+    cols = np.arange(lo, hi, dtype=np.int64)
+    return (cols[None, :] + ncols * np.arange(problem.nz, dtype=np.int64)[:, None]).ravel()
+
+
+def paper_plans(problem: Problem, count: int, prob: float = 0.02, data_loss: float = 0.01,
+                procs: int = 36, max_events: int = 10, horizon: int = 1000, seed0: int = SEEDS["paper_plan0"],
+                bit_max: int = 63) -> List[Plan]:
+    """The paper's fault model (Section 3), one plan per run: after the
+    preconditioner of every executed step a fault event happens with
+    probability `prob`, at most `max_events` per run; an event hits one
+    process drawn at random (one of `procs` bands of whole columns) and
+    flips one random bit U{0..bit_max} in each of ceil(data_loss * N)
+    distinct entries of that process' share of e = P^-1(r) (all of its
+    entries when the share is smaller).  Steps are drawn up to `horizon`;
+    events past the end of a run are not applied."""
+    plans = []
+    n = problem.n
+    cnt = max(1, int(math.ceil(data_loss * n)))
+    for m in range(count):
+        rng = np.random.default_rng(seed0 + m)
+        hits = np.nonzero(rng.random(horizon) < prob)[0][:max_events] + 1
+        plan: Plan = []
+        for step in hits.tolist():
+            own = process_entries(problem, procs, int(rng.integers(0, procs)))
+            idx = own if cnt >= own.size else np.sort(rng.choice(own, cnt, replace=False))
+            bits = rng.integers(0, bit_max + 1, idx.size).astype(np.uint8)
+            plan.append(FaultEvent(step=int(step), vec=VEC_E, bit=0, idx=idx.astype(np.int64), bits=bits))
+        plans.append(plan)
+    return plans
 
 
 @dataclasses.dataclass
