@@ -95,16 +95,22 @@ typedef struct {
     int32_t pad_;
 } ftgcr_options;
 
-/* Fault injection (test harness).  At the start of executed inner step `step`
- * (1-based, counted over the whole solve), before the step reads anything,
- * XOR bit `bit` (or bits[t] per entry) into the IEEE-754 pattern of entries of
- * one working vector: the iterate x (binary64), the residual r, the current
- * direction p^nu, or its image L(p^nu) (binary64 in FP64 handles, binary32 in
- * MIXED handles: bits 0..31).  idx == NULL means the range [start,
- * start+count).  The paper flips bits of e = P^{-1}(r) (Section 3); this
- * ABI targets the vectors the workload configurations name.  An event whose
- * step is never reached is not applied. */
-typedef enum { FTGCR_V_X = 0, FTGCR_V_R = 1, FTGCR_V_P = 2, FTGCR_V_AP = 3 } ftgcr_vec;
+/* Fault injection (test harness).  XOR bit `bit` (or bits[t] per entry) into
+ * the IEEE-754 pattern of entries of one working vector (binary64 in FP64
+ * handles, binary32 in MIXED handles: bits 0..31; the iterate x is always
+ * binary64) during executed inner step `step` (1-based, counted over the
+ * whole solve):
+ *   X, R, P, AP  the iterate x, the residual r, the current direction p^nu or
+ *                its image L(p^nu), at the start of the step, before the step
+ *                reads anything;
+ *   E            the preconditioner output e = P^{-1}(r+) of the step, right
+ *                after the column solve and before L(e) and the new direction
+ *                read it: the paper's injection site (Section 3).  Applied
+ *                only when the step passes its exit and fault tests (otherwise
+ *                e is never used).
+ * idx == NULL means the range [start, start+count).  An event whose step is
+ * never reached is not applied. */
+typedef enum { FTGCR_V_X = 0, FTGCR_V_R = 1, FTGCR_V_P = 2, FTGCR_V_AP = 3, FTGCR_V_E = 4 } ftgcr_vec;
 typedef struct {
     int64_t step;
     int32_t vec;           /* ftgcr_vec                                         */

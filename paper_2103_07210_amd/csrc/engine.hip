@@ -376,11 +376,15 @@ struct Runner {
         return FTGCR_OK;
     }
 
-    void step(long long number)
+    // One inner step; `mid` are the step's e events (injected after the
+    // column solve's decision, before the stencil pass reads e).
+    void step(long long number, const std::vector<const DevEvent*>* mid = nullptr)
     {
         cur_step = number;
         timed(0, [&] { L::update_thomas(tb, h->nblk_col, h->H, 0, s); });
         L::finish_col(tb, 0, s);
+        if (mid)
+            for (const DevEvent* ev : *mid) event(*ev);
         timed(1, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
         L::finish_alpha(tb, s);
         timed(2, [&] { L::dir_update(tb, h->nblk_st, h->kc, 0, s); });
@@ -401,7 +405,7 @@ struct Runner {
         const int gcopy = (int)std::min<long long>((n + 255) / 256, 8192);
         const int ginj = (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192));
         L::event_prep(tb, ev.vec, s);
-        L::event_copy(tb, gcopy, s);
+        if (ev.vec != FTGCR_V_E) L::event_copy(tb, gcopy, s);
         L::event_inject(tb, ginj, ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
         if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) {
             L::beta_dots(tb, h->nblk_st, s);
@@ -439,8 +443,12 @@ struct Runner {
         while (true) {
             while (evp < evs.size() && evs[evp].step <= launched) ++evp;
             if (evp < evs.size() && evs[evp].step == launched + 1) {
-                while (evp < evs.size() && evs[evp].step == launched + 1) event(evs[evp++]);
-                step(launched + 1);
+                std::vector<const DevEvent*> mid;
+                for (; evp < evs.size() && evs[evp].step == launched + 1; ++evp) {
+                    if (evs[evp].vec == FTGCR_V_E) mid.push_back(&evs[evp]);
+                    else event(evs[evp]);
+                }
+                step(launched + 1, &mid);
                 launched += 1;
                 issued += 1;
             } else {
@@ -475,7 +483,7 @@ ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::ve
     size_t need = 0;
     for (int q = 0; q < plan->n_events; ++q) {
         const ftgcr_fault_event& e = plan->events[q];
-        if (e.vec < FTGCR_V_X || e.vec > FTGCR_V_AP) return fail(h, FTGCR_E_INVALID, "event vec out of range");
+        if (e.vec < FTGCR_V_X || e.vec > FTGCR_V_E) return fail(h, FTGCR_E_INVALID, "event vec out of range");
         if (e.count < 0) return fail(h, FTGCR_E_INVALID, "event count < 0");
         const int bmax = (e.vec == FTGCR_V_X) ? 63 : maxbit;
         if (!e.bits && (e.bit < 0 || e.bit > bmax)) return fail(h, FTGCR_E_INVALID, "event bit out of range");
@@ -777,19 +785,26 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     std::vector<size_t> evp(n, 0);
     std::vector<long long> host_status(2 * n);
     while (!members.empty()) {
-        // fault events of the next step, member by member
+        // fault events of the next step, member by member: x, r, p, L(p)
+        // events now, e events between the step's decision and its stencil
+        // pass
+        auto apply = [&](int m, const DevEvent& ev) {
+            const Table<double> t1 = single(m);
+            const long long nn = hs[m]->geo.n;
+            L::event_prep(t1, ev.vec, s);
+            if (ev.vec != FTGCR_V_E) L::event_copy(t1, (int)std::min<long long>((nn + 255) / 256, 8192), s);
+            L::event_inject(t1, (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192)),
+                            ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
+            if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) L::beta_dots(t1, ins[m].nblk_st, s);
+        };
         bool any_event = false;
+        std::vector<std::pair<int, const DevEvent*>> mid;
         for (int m : members) {
             while (evp[m] < evs[m].size() && evs[m][evp[m]].step <= launched) ++evp[m];
             while (evp[m] < evs[m].size() && evs[m][evp[m]].step == launched + 1) {
                 const DevEvent& ev = evs[m][evp[m]++];
-                const Table<double> t1 = single(m);
-                const long long nn = hs[m]->geo.n;
-                L::event_prep(t1, ev.vec, s);
-                L::event_copy(t1, (int)std::min<long long>((nn + 255) / 256, 8192), s);
-                L::event_inject(t1, (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192)),
-                                ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
-                if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) L::beta_dots(t1, ins[m].nblk_st, s);
+                if (ev.vec == FTGCR_V_E) mid.push_back({m, &ev});
+                else apply(m, ev);
                 any_event = true;
             }
         }
@@ -799,6 +814,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         for (long long q = 0; q < cnt; ++q) {
             L::update_thomas(tb, bt.cols, H, 0, s);
             L::finish_col(tb, 0, s);
+            for (const auto& me : mid) apply(me.first, *me.second);   // cnt == 1 whenever mid is not empty
             L::stencil_dots(tb, bt.sts, kc, s);
             L::finish_alpha(tb, s);
             L::dir_update(tb, bt.sts, kc, 0, s);

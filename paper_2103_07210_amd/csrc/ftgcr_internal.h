@@ -75,7 +75,7 @@ struct SolveState {
     int ev_src, ev_dst;  // buffer indices for the copy
     int ev_lo, ev_hi;    // x materialisation: beta terms l in [lo, hi)
     int log_len;
-    int pad_;
+    int e_ok;            // 1: this step passed its tests, its e feeds a new direction
     DetectRec log[LOG_CAP];
 };
 

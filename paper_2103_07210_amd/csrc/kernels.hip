@@ -619,6 +619,7 @@ __device__ void decide_step(SolveState* st, double rn, double rs, double* hist, 
 {
     const int nu = st->nu;
     st->s += 1;
+    st->e_ok = 0;
     const long long s = st->s;
     if (st->d_cur == 0.0) {   // <L p, L p> = 0: beta undefined
         st->status = FTGCR_BREAKDOWN;
@@ -677,6 +678,7 @@ __device__ void decide_step(SolveState* st, double rn, double rs, double* hist, 
     st->rr_old = rs;
     st->r_cur = st->r_dst;
     st->active = 1;
+    st->e_ok = 1;
     if (s >= st->max_steps) {
         st->status = FTGCR_MAX_STEPS;
         st->x_final_hi = nu;
@@ -1168,10 +1170,14 @@ __global__ void k_event_prep(Table<T> tb, int vec)
 {
     if (threadIdx.x != 0) return;
     SolveState* st = tb.inst[0].st;
-    st->ev_ok = (st->status == RUNNING);
+    // e events run between the step's decision and its stencil pass: they
+    // apply when the step passed its tests (its e feeds the new direction);
+    // e belongs to no backup, so nothing is copied first
+    st->ev_ok = (vec == FTGCR_V_E) ? st->e_ok : (st->status == RUNNING);
     if (!st->ev_ok) return;
     st->ev_vec = vec;
     st->ev_copy = 0;
+    if (vec == FTGCR_V_E) return;
     const int nu = st->nu;
     if (vec == FTGCR_V_X) {
         // materialise the iterate of this step: x_base + sum_{l < nu} beta_l p^l
@@ -1245,7 +1251,8 @@ __global__ void k_event_inject(Table<T> tb, const long long* idx, const unsigned
         if (vec == FTGCR_V_X) write_xor<double>(in.X[st->x_base] + at, bit);
         else if (vec == FTGCR_V_R) write_xor<T>(in.R[st->r_cur] + at, bit);
         else if (vec == FTGCR_V_P) write_xor<T>(in.P[st->slot[st->nu]] + at, bit);
-        else write_xor<T>(in.AP[st->slot[st->nu]] + at, bit);
+        else if (vec == FTGCR_V_AP) write_xor<T>(in.AP[st->slot[st->nu]] + at, bit);
+        else write_xor<T>(in.E + at, bit);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->events_applied += 1;
