@@ -63,7 +63,11 @@ def summarize(records: Sequence[Dict], clean_steps: int) -> Dict:
 
 
 def run(problem, plans, k: int = 4, tol: float = 1e-10, with_unprotected: bool = True, rhs_seed: int = 2,
-        precision: str = "fp64"):
+        precision: str = "fp64", cap_factor: float = 0.0):
+    """One protected (and optionally one unprotected) solve per plan.  With
+    cap_factor > 0 every faulty solve stops after cap_factor times the
+    fault-free step count (an unprotected run that took an Inf or NaN never
+    converges); such runs count at the cap and are reported."""
     import torch
     from . import ftgcr
     from . import inputs as I
@@ -71,6 +75,11 @@ def run(problem, plans, k: int = 4, tol: float = 1e-10, with_unprotected: bool =
     on = ftgcr.Solver(problem, precision, kmax=k)
     off = ftgcr.Solver(problem, precision, kmax=k, ft=0) if with_unprotected else None
     x_clean, st_clean = on.solve(rhs, tol=tol, k=k)
+    if cap_factor > 0:
+        cap = int(cap_factor * max(st_clean["steps_executed"], 1))
+        on.set_options(max_steps=cap)
+        if off is not None:
+            off.set_options(max_steps=cap)
     x_clean = x_clean.clone()
     nrm = float(torch.linalg.norm(x_clean))
     names = {0: "x", 1: "r", 2: "p", 3: "ap", 4: "e"}
@@ -82,13 +91,15 @@ def run(problem, plans, k: int = 4, tol: float = 1e-10, with_unprotected: bool =
                "count": int(first.count) if first else 0, "bit": int(first.bit) if first else -1,
                "step": int(first.step) if first else 0, "events_planned": len(plan),
                "events_applied": st["events_applied"], "detections": st["detections"],
-               "steps": st["steps_executed"], "cycles": st["cycles"], "status": st["status"]}
+               "steps": st["steps_executed"], "cycles": st["cycles"], "status": st["status"],
+               "converged": st["status"] == ftgcr.CONVERGED}
         d = torch.nan_to_num(x - x_clean, nan=np.inf, posinf=np.inf, neginf=np.inf)
         rec["err"] = float(torch.linalg.norm(d)) / nrm
         if off is not None:
             xo, so = off.solve(rhs, tol=tol, k=k, plan=plan)
             d = torch.nan_to_num(xo - x_clean, nan=np.inf, posinf=np.inf, neginf=np.inf)
             rec["steps_off"] = so["steps_executed"]
+            rec["converged_off"] = so["status"] == ftgcr.CONVERGED
             rec["cycles_off"] = so["cycles"]
             rec["events_applied_off"] = so["events_applied"]
             rec["err_off"] = float(torch.linalg.norm(d)) / nrm
@@ -104,7 +115,8 @@ def summarize_paper(records: Sequence[Dict], clean_steps: int, clean_cycles: int
     fault applied (the paper disregards fault-free runs): faults per run,
     faults detected per run, detection rate (the per-run mean of detected /
     applied, in percent), mean iterations with and without fault tolerance
-    and RoFT, in executed steps and in outer cycles (the paper's unit)."""
+    and RoFT, in executed steps and in outer cycles (the paper's unit).
+    Runs stopped by the step cap count at the cap and are reported."""
     faulty = [r for r in records if r["events_applied"] > 0]
     out = {"runs": len(records), "runs_with_fault": len(faulty), "baseline_steps": clean_steps,
            "baseline_cycles": clean_cycles}
@@ -113,10 +125,12 @@ def summarize_paper(records: Sequence[Dict], clean_steps: int, clean_cycles: int
     out["faults_per_run"] = float(np.mean([r["events_applied"] for r in faulty]))
     out["detected_per_run"] = float(np.mean([r["detections"] for r in faulty]))
     out["detection_rate_percent"] = 100.0 * float(np.mean([r["detections"] / r["events_applied"] for r in faulty]))
+    out["not_converged_ft"] = int(sum(not r.get("converged", True) for r in faulty))
     out["mean_steps_ft"] = float(np.mean([r["steps"] for r in faulty]))
     out["mean_cycles_ft"] = float(np.mean([r["cycles"] for r in faulty]))
     out["final_error_ft_max"] = float(np.max([r["err"] for r in faulty]))
     if all("steps_off" in r for r in faulty):
+        out["not_converged_noft"] = int(sum(not r.get("converged_off", True) for r in faulty))
         out["mean_steps_noft"] = float(np.mean([r["steps_off"] for r in faulty]))
         out["mean_cycles_noft"] = float(np.mean([r["cycles_off"] for r in faulty]))
         out["roft_percent_steps"] = roft(out["mean_steps_noft"], out["mean_steps_ft"], clean_steps)
@@ -136,6 +150,7 @@ def main():
     ap.add_argument("--prob", type=float, default=0.02)
     ap.add_argument("--loss", default="4e-6,4e-4,2e-3,0.01,0.05,0.2")
     ap.add_argument("--procs", type=int, default=36)
+    ap.add_argument("--cap", type=float, default=4.0, help="paper model: step cap as a multiple of the fault-free count")
     args = ap.parse_args()
     pb = I.Problem(*[int(v) for v in args.grid.split(",")])
     import torch
@@ -149,7 +164,8 @@ def main():
         return
     for loss in [float(v) for v in args.loss.split(",")]:
         plans = I.paper_plans(pb, args.count, prob=args.prob, data_loss=loss, procs=args.procs)
-        records, _, st_clean = run(pb, plans, k=args.k, tol=args.tol, rhs_seed=I.SEEDS["c2_rhs"])
+        records, _, st_clean = run(pb, plans, k=args.k, tol=args.tol, rhs_seed=I.SEEDS["c2_rhs"],
+                                   cap_factor=args.cap)
         summary = summarize_paper(records, st_clean["steps_executed"], st_clean["cycles"])
         summary.update({"grid": [pb.nx, pb.ny, pb.nz], "k": args.k, "prob": args.prob,
                         "data_loss_percent": 100.0 * loss, "procs": args.procs})
