@@ -296,11 +296,12 @@ __device__ __forceinline__ float lane_read(float v, int l)
 // is used; missing neighbours (beyond the poles, bottom, top) are selected
 // to 0 (a select, not a product, so a NaN at a clamped address cannot leak)
 // and carry weight 0.  Entries at levels >= nz or in clamped columns are
-// garbage and must be masked by the caller.  Every thread of the block must
-// call this (it holds a barrier).
+// garbage and must be masked by the caller.  `centre`, if given, receives
+// x at the KC levels (as loaded).  Every thread of the block must call this
+// (it holds a barrier).
 template <typename TI, int KC>
 __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict__ x, int i, int j,
-                                              int k0, double (&out)[KC])
+                                              int k0, double (&out)[KC], double* centre = nullptr)
 {
     static_assert(ST_TX == 64 && ST_TY * ST_TX == ST_THREADS, "one wavefront per tile row");
     static_assert(KC <= 32, "edge lanes");
@@ -402,6 +403,7 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
         off = fma(wa, xa, off);
         const AT diag = opsig * ((fma(gk, rc.h1, rc.h0) + wb) + wa);
         out[kk] = (double)fma(diag, xv[kk + 1], -off);
+        if (centre) centre[kk] = (double)xv[kk + 1];
     }
 }
 
@@ -976,22 +978,39 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
     for (int kk = 0; kk < KC; ++kk)
         if (!(ps.col_ok && ps.k0 + kk < nz)) le[kk] = 0.0;
     // every <L(e), L(p^l)>: one uniform branch per l, its KC loads batched
+    // every <L(e), L(p^l)>, one uniform branch per l; the loads of term
+    // l + 1 are issued before term l's values are used (a two-stage
+    // pipeline), so the terms cost one memory round trip together, not one
+    // each
+    // (two buffers alternating with the parity of l, which is a compile-time
+    // constant after unrolling: no register copies, so the wait for term l
+    // comes after term l + 1's loads are issued)
     double acc[KMAX + 1];
+    T buf[2][KC];
+    {
+        const gptr<T> ap0 = as_global(s_ap[0]);
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+            buf[0][kk] = ap0[c0 + plane * kq];
+        }
+    }
 #pragma unroll
     for (int l = 0; l <= KMAX; ++l) {
         acc[l] = 0.0;
         if (l <= nu) {
-            const gptr<T> apl = as_global(s_ap[l]);
-            double av[KC];
+            if (l < KMAX && l + 1 <= nu) {
+                const gptr<T> apn = as_global(s_ap[l + 1]);
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk) {
-                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-                av[kk] = (double)apl[c0 + plane * kq];
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                    buf[(l + 1) & 1][kk] = apn[c0 + plane * kq];
+                }
             }
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
                 const bool ok = ps.col_ok && ps.k0 + kk < nz;
-                acc[l] = fma(le[kk], ok ? av[kk] : 0.0, acc[l]);
+                acc[l] = fma(le[kk], ok ? (double)buf[l & 1][kk] : 0.0, acc[l]);
             }
         }
     }
@@ -1062,34 +1081,48 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double a[KC], p[KC], xa[KC], r[KC];
-    stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a);
+    // p starts from e: the stencil's own centre values (no second load)
+    stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a, p);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
         const long long c = c0 + plane * kq;
-        p[kk] = (double)in.E[c];
         r[kk] = (double)rv[c];
         xa[kk] = xupd ? xb[c] : 0.0;
+    }
+    // sums over l in ascending order; term l + 1's loads are issued before
+    // term l's values are used (two-stage pipeline, as in the dots pass)
+    T pb[2][KC], ab[2][KC];
+    if (nu >= 0) {
+        const gptr<T> p0 = as_global(s_p[0]);
+        const gptr<T> ap0 = as_global(s_ap[0]);
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+            pb[0][kk] = p0[c0 + plane * kq];
+            ab[0][kk] = ap0[c0 + plane * kq];
+        }
     }
 #pragma unroll
     for (int l = 0; l < KMAX; ++l) {
         if (l <= nu) {
-            const gptr<T> pl = as_global(s_p[l]);
-            const gptr<T> apl = as_global(s_ap[l]);
             const double al = s_al[l];
             const double bl = s_be[l];
-            double pv[KC], av[KC];
+            if (l + 1 < KMAX && l + 1 <= nu) {
+                const gptr<T> pn = as_global(s_p[l + 1]);
+                const gptr<T> apn = as_global(s_ap[l + 1]);
 #pragma unroll
-            for (int kk = 0; kk < KC; ++kk) {
-                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-                pv[kk] = (double)pl[c0 + plane * kq];
-                av[kk] = (double)apl[c0 + plane * kq];
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                    pb[(l + 1) & 1][kk] = pn[c0 + plane * kq];
+                    ab[(l + 1) & 1][kk] = apn[c0 + plane * kq];
+                }
             }
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
-                p[kk] = fma(al, pv[kk], p[kk]);
-                a[kk] = fma(al, av[kk], a[kk]);
-                if (xupd) xa[kk] = fma(bl, pv[kk], xa[kk]);
+                p[kk] = fma(al, (double)pb[l & 1][kk], p[kk]);
+                a[kk] = fma(al, (double)ab[l & 1][kk], a[kk]);
+                if (xupd) xa[kk] = fma(bl, (double)pb[l & 1][kk], xa[kk]);
             }
         }
     }
