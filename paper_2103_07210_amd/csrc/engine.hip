@@ -51,7 +51,7 @@ struct ftgcr_handle {
     SolveState* st = nullptr;       // device control state
     void* inst = nullptr;           // device Inst<T> of the storage type
     Inst<double>* inst_dbg = nullptr;  // device Inst<double> for the parity entry points
-    int* blk0 = nullptr;            // device {0, nblk_col, 0, nblk_st}
+    int* blk0 = nullptr;            // device {0, nblk_col, 0, nblk_st, 0, nblk_dir}
     SolveState* st_host = nullptr;  // pinned copy for reading back
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 
@@ -67,8 +67,8 @@ struct ftgcr_handle {
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
 
-    int nblk_col = 0, nblk_st = 0;
-    int kc = 1, tx = 1, ty = 1, tz = 1, H = 4;
+    int nblk_col = 0, nblk_st = 0, nblk_dir = 0;
+    int kc = 1, tx = 1, ty = 1, tz = 1, H = 4, kc_dir = 1, tz_dir = 1;
     int tuned_kc = 0;   // from ftgcr_autotune (0: none)
 
     // kernel timing (options.profile_kernels)
@@ -137,6 +137,17 @@ int auto_levels_per_block(int tx, int ty, int nz)
     return 1;
 }
 
+// The direction pass holds two values per direction term and level (p^l and
+// L(p^l), two pipeline stages), so it takes at most 4 levels per block: at 8
+// its FP64 form needs more than 128 registers and drops to two waves per SIMD
+// (measured 125 vs 118 us on 512x256x64, while the dots pass is fastest at 8).
+void dir_tiling(int kc, int nz, int tx, int ty, int& kc_dir, int& tz_dir, int& nblk_dir)
+{
+    kc_dir = kc < 4 ? kc : 4;
+    tz_dir = (nz + kc_dir - 1) / kc_dir;
+    nblk_dir = tx * ty * tz_dir;
+}
+
 void set_tiling(ftgcr_handle* h)
 {
     const Geo& g = h->geo;
@@ -149,6 +160,7 @@ void set_tiling(ftgcr_handle* h)
     h->kc = kc;
     h->tz = (g.nz + kc - 1) / kc;
     h->nblk_st = h->tx * h->ty * h->tz;
+    dir_tiling(kc, g.nz, h->tx, h->ty, h->kc_dir, h->tz_dir, h->nblk_dir);
 }
 
 size_t elem_bytes(const ftgcr_handle* h) { return h->precision == FTGCR_MIXED ? 4 : 8; }
@@ -202,6 +214,9 @@ Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x)
     in.tx = h->tx;
     in.ty = h->ty;
     in.tz = h->tz;
+    in.nblk_dir = h->nblk_dir;
+    in.kc_dir = h->kc_dir;
+    in.tz_dir = h->tz_dir;
     return in;
 }
 
@@ -271,8 +286,11 @@ ftgcr_status upload_debug_inst(ftgcr_handle* h)
     in.tx = h->tx;
     in.ty = h->ty;
     in.tz = h->tz;
+    in.nblk_dir = h->nblk_dir;
+    in.kc_dir = h->kc_dir;
+    in.tz_dir = h->tz_dir;
     HIP_TRY(h, hipMemcpy(h->inst_dbg, &in, sizeof in, hipMemcpyHostToDevice));
-    const int blk0[4] = {0, h->nblk_col, 0, h->nblk_st};
+    const int blk0[6] = {0, h->nblk_col, 0, h->nblk_st, 0, h->nblk_dir};
     HIP_TRY(h, hipMemcpy(h->blk0, blk0, sizeof blk0, hipMemcpyHostToDevice));
     return FTGCR_OK;
 }
@@ -387,7 +405,7 @@ struct Runner {
             for (const DevEvent* ev : *mid) event(*ev);
         timed(1, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
         L::finish_alpha(tb, s);
-        timed(2, [&] { L::dir_update(tb, h->nblk_st, h->kc, 0, s); });
+        timed(2, [&] { L::dir_update(tb, h->nblk_dir, h->kc_dir, 0, s); });
         L::finish_beta(tb, 0, s);
     }
 
@@ -395,7 +413,7 @@ struct Runner {
     {
         L::update_thomas(tb, h->nblk_col, h->H, 1, s);
         L::finish_col(tb, 1, s);
-        L::dir_update(tb, h->nblk_st, h->kc, 1, s);
+        L::dir_update(tb, h->nblk_dir, h->kc_dir, 1, s);
         L::finish_beta(tb, 1, s);
     }
 
@@ -576,7 +594,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     Inst<T> in = make_inst<T>(h, rhs, x);
     HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, 1}, s};
+    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1}, s};
     const Table<T>& tb = run.tb;
     const bool mixed = h->precision == FTGCR_MIXED;
     const long long max_steps = h->opt.max_steps;
@@ -657,9 +675,9 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
 
 struct BatchTables {
     Inst<double>* inst = nullptr;   // device
-    int* blk0 = nullptr;            // device: col prefix (n+1), st prefix (n+1)
+    int* blk0 = nullptr;            // device: col, st and dir prefixes (n+1 each)
     long long* status = nullptr;    // device: 2 per member
-    int cols = 0, sts = 0;
+    int cols = 0, sts = 0, dirs = 0;
 };
 
 ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins, const std::vector<int>& members,
@@ -667,17 +685,19 @@ ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins
 {
     const int na = (int)members.size();
     std::vector<Inst<double>> act(na);
-    std::vector<int> pre(2 * (na + 1), 0);
+    std::vector<int> pre(3 * (na + 1), 0);
     for (int q = 0; q < na; ++q) {
         act[q] = ins[members[q]];
         pre[q + 1] = pre[q] + act[q].nblk_col;
         pre[na + 1 + q + 1] = pre[na + 1 + q] + act[q].nblk_st;
+        pre[2 * (na + 1) + q + 1] = pre[2 * (na + 1) + q] + act[q].nblk_dir;
     }
     HIP_TRY(h0, hipMemcpy(bt.inst, act.data(), na * sizeof(Inst<double>), hipMemcpyHostToDevice));
     HIP_TRY(h0, hipMemcpy(bt.blk0, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
     bt.cols = pre[na];
     bt.sts = pre[2 * na + 1];
-    tb = Table<double>{bt.inst, bt.blk0, bt.blk0 + na + 1, na};
+    bt.dirs = pre[3 * na + 2];
+    tb = Table<double>{bt.inst, bt.blk0, bt.blk0 + na + 1, bt.blk0 + 2 * (na + 1), na};
     return FTGCR_OK;
 }
 
@@ -706,6 +726,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         ins[m].kc = kc;
         ins[m].tz = (h->geo.nz + kc - 1) / kc;
         ins[m].nblk_st = ins[m].tx * ins[m].ty * ins[m].tz;
+        dir_tiling(kc, h->geo.nz, ins[m].tx, ins[m].ty, ins[m].kc_dir, ins[m].tz_dir, ins[m].nblk_dir);
         ftgcr_status rc = stage_events(h, plans ? &plans[m] : nullptr, evs[m]);
         if (rc != FTGCR_OK) {
             if (m) h0->err = h->err;
@@ -719,7 +740,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         if (bt.status) (void)hipFree(bt.status);
     };
     if (hipMalloc(&bt.inst, n * sizeof(Inst<double>)) != hipSuccess ||
-        hipMalloc(&bt.blk0, 2 * (n + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&bt.blk0, 3 * (n + 1) * sizeof(int)) != hipSuccess ||
         hipMalloc(&bt.status, 2 * n * sizeof(long long)) != hipSuccess) {
         cleanup();
         return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
@@ -744,10 +765,11 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     // the full table keeps its own prefix arrays (the launch table is
     // compacted in place as members finish)
     int* blk0_all = nullptr;
-    std::vector<int> pre_all(2 * (n + 1), 0);
+    std::vector<int> pre_all(3 * (n + 1), 0);
     for (int m = 0; m < n; ++m) {
         pre_all[m + 1] = pre_all[m] + ins[m].nblk_col;
         pre_all[n + 1 + m + 1] = pre_all[n + 1 + m] + ins[m].nblk_st;
+        pre_all[2 * (n + 1) + m + 1] = pre_all[2 * (n + 1) + m] + ins[m].nblk_dir;
     }
     if (hipMalloc(&blk0_all, pre_all.size() * sizeof(int)) != hipSuccess ||
         hipMemcpy(blk0_all, pre_all.data(), pre_all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
@@ -759,7 +781,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         cleanup_all();
         (void)hipFree(blk0_all);
     };
-    const Table<double> tb_all{all, blk0_all, blk0_all + n + 1, n};
+    const Table<double> tb_all{all, blk0_all, blk0_all + n + 1, blk0_all + 2 * (n + 1), n};
     const int sts_all = pre_all[2 * n + 1];
     Table<double> tb{};
     ftgcr_status rc = upload_batch(h0, ins, members, bt, tb);
@@ -767,7 +789,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         cleanup_full();
         return rc;
     }
-    auto single = [&](int m) { return Table<double>{all + m, hs[m]->blk0, hs[m]->blk0 + 2, 1}; };
+    auto single = [&](int m) { return Table<double>{all + m, hs[m]->blk0, hs[m]->blk0 + 2, hs[m]->blk0 + 4, 1}; };
 
     hipEvent_t e0 = h0->ev_start, e1 = h0->ev_stop;
     (void)hipEventRecord(e0, s);
@@ -776,7 +798,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     L::residual(tb, bt.sts, kc, 1, 1, s);
     L::update_thomas(tb, bt.cols, H, 1, s);
     L::finish_col(tb, 1, s);
-    L::dir_update(tb, bt.sts, kc, 1, s);
+    L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 1, s);
     L::finish_beta(tb, 1, s);
 
     const int chunk = std::max(1, h0->opt.poll_steps);
@@ -817,7 +839,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
             for (const auto& me : mid) apply(me.first, *me.second);   // cnt == 1 whenever mid is not empty
             L::stencil_dots(tb, bt.sts, kc, s);
             L::finish_alpha(tb, s);
-            L::dir_update(tb, bt.sts, kc, 0, s);
+            L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 0, s);
             L::finish_beta(tb, 0, s);
         }
         launched += cnt;
@@ -947,7 +969,7 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
         hipMemset(h->st, 0, sizeof(SolveState)) != hipSuccess ||
         hipMalloc(&h->inst, std::max(sizeof(Inst<double>), sizeof(Inst<float>))) != hipSuccess ||
         hipMalloc(&h->inst_dbg, sizeof(Inst<double>)) != hipSuccess ||
-        hipMalloc(&h->blk0, 4 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&h->blk0, 6 * sizeof(int)) != hipSuccess ||
         hipHostMalloc(&h->st_host, sizeof(SolveState)) != hipSuccess ||
         hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_stop) != hipSuccess) {
         h->err = "device allocation failed";
@@ -1154,7 +1176,7 @@ ftgcr_status ftgcr_debug_apply_A(ftgcr_handle* h, const double* in_dev, double* 
     if (!h) return FTGCR_E_INVALID;
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
-    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, 1};
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
     Launch<double>::debug_apply_A(tb, h->nblk_st, h->kc, in_dev, out_dev, h->stream);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -1166,7 +1188,7 @@ ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, doubl
     if (!h) return FTGCR_E_INVALID;
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
-    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, 1};
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
     Launch<double>::debug_pinv(tb, h->nblk_col, h->H, in_dev, out_dev, h->stream);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));

@@ -114,6 +114,9 @@ struct Inst {
     int nblk_st;             // blocks of the stencil grid
     int kc;                  // stencil levels per block
     int tx, ty, tz;          // stencil tiles per dimension
+    // the direction pass (the most registers per level) has its own level
+    // tiling over the same columns
+    int nblk_dir, kc_dir, tz_dir;
 };
 
 // Launch table for combined (batched) launches: block b of a launch belongs
@@ -123,6 +126,7 @@ struct Table {
     const Inst<T>* inst;
     const int* blk0_col;     // n + 1 prefix sums (column grid)
     const int* blk0_st;      // n + 1 prefix sums (stencil grid)
+    const int* blk0_dir;     // n + 1 prefix sums (direction-pass grid)
     int n;
 };
 

@@ -415,7 +415,7 @@ struct StPos {
 };
 
 template <typename T>
-__device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb)
+__device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb, int kc)
 {
     StPos p;
     const int bx = lb % in.tx;
@@ -427,8 +427,14 @@ __device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb)
     p.col_ok = i < in.g.nx && j < in.g.ny;
     p.i = i < in.g.nx ? i : in.g.nx - 1;
     p.j = j < in.g.ny ? j : in.g.ny - 1;
-    p.k0 = bz * in.kc;
+    p.k0 = bz * kc;
     return p;
+}
+
+template <typename T>
+__device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb)
+{
+    return st_pos(in, lb, in.kc);
 }
 
 template <typename T>
@@ -1053,9 +1059,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
     __shared__ const T* s_ap[KMAX + 1];
     __shared__ double s_al[KMAX + 1];
     __shared__ double s_be[KMAX + 1];
-    const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
+    const int m = find_inst(tb.blk0_dir, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
-    const int lb = blockIdx.x - tb.blk0_st[m];
+    const int lb = blockIdx.x - tb.blk0_dir[m];
     SolveState* st = in.st;
     if (st->status != RUNNING) return;
     if (!init && !st->active) return;
@@ -1076,7 +1082,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
         s_be[threadIdx.x] = (xupd && (int)threadIdx.x >= xlo) ? st->beta[threadIdx.x] : 0.0;
     }
     __syncthreads();
-    const StPos ps = st_pos(in, lb);
+    const StPos ps = st_pos(in, lb, in.kc_dir);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
@@ -1159,7 +1165,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int in
     if (st->status != RUNNING) return;
     if (!init && !st->active) return;
     double v[2];
-    sum_partials(in, in.nblk_st, 2, v);
+    sum_partials(in, in.nblk_dir, 2, v);
     const double num = v[0], dn = v[1];
     if (threadIdx.x == 0) decide_beta(st, num, dn, init);
 }

@@ -119,3 +119,22 @@ def test_generators_follow_the_configurations():
     assert all(0.2 <= m.problem.hill_amp <= 1.0 for m in ens)
     blk = I.block_plan(I.C5)[0]
     assert blk.count == int(np.ceil(0.1 * I.C5.n)) and blk.start + blk.count <= I.C5.n
+
+
+def _header_enum(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef enum \{([^}]*)\}\s*" + name + ";", text)
+    assert m, name
+    return {k.strip(): int(v) for k, v in (item.split("=") for item in m.group(1).split(","))}
+
+
+def test_fault_targets_agree_with_header_and_oracle():
+    """The vector codes of fault events: header enum, the generators' codes
+    and the oracle header's codes are the same numbers (plans go to both)."""
+    hdr = _header_enum("ftgcr_vec")
+    assert hdr == {"FTGCR_V_X": 0, "FTGCR_V_R": 1, "FTGCR_V_P": 2, "FTGCR_V_AP": 3, "FTGCR_V_E": 4}
+    assert I.VEC_NAMES == {"x": 0, "r": 1, "p": 2, "ap": 3, "e": 4}
+    otext = open(os.path.join(ROOT, "oracle", "ftgcr_oracle.h")).read()
+    m = re.search(r"enum \{ (ORC_V_X = 0[^}]*)\}", otext)
+    codes = {k.strip(): int(v) for k, v in (item.split("=") for item in m.group(1).split(","))}
+    assert list(codes.values()) == list(hdr.values())
