@@ -248,6 +248,31 @@ def main():
         for sv in solvers:
             sv.close()
 
+    # the two small configurations (cache-resident, launch- and
+    # latency-bound: timed, not priced against the HBM roofline)
+    small = None
+    if not args.no_large:
+        small = {}
+        for name, pbs, kk, rs in (("64x32x8", I.C1, 3, I.SEEDS["c1_rhs"]), ("256x128x32", I.C2, 4, I.SEEDS["c2_rhs"])):
+            rhs_s = torch.from_numpy(I.rhs(pbs, rs)).cuda()
+            ss = ftgcr.Solver(pbs, "fp64", kmax=kk, poll_steps=32)
+            ss.autotune(rhs_s, k=kk, steps=12)
+            xs_ = torch.zeros_like(rhs_s)
+            ss.solve(rhs_s, xs_, tol=1e-10, k=kk)
+            runs_s = []
+            for _ in range(5):
+                xs_.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, sts = ss.solve(rhs_s, xs_, tol=1e-10, k=kk)
+                torch.cuda.synchronize()
+                runs_s.append((time.perf_counter() - t1) * 1e3)
+            ms_s = float(np.median(runs_s))
+            small[name] = {"k": kk, "tol": 1e-10, "ms": ms_s, "steps": sts["steps_executed"],
+                           "steps_per_s": sts["steps_executed"] / ms_s * 1e3}
+            print(f"[bench] {name}: {ms_s:.2f} ms, {sts['steps_executed']} steps", flush=True)
+            ss.close()
+
     # the 1024 x 512 x 96 problem (one GPU's share of an 8-GPU run at
     # 8x the columns): FP64 and mixed, fault-free and with a 10% contiguous
     # block of r flipped (exponent MSB) at step 10
@@ -310,6 +335,7 @@ def main():
         "kernels": kernels,
         "ensemble_64": ensemble,
         "large_1024x512x96": large,
+        "small_configs": small,
         "copy_probe_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic if dom == "dir_update" else None,

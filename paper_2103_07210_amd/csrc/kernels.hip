@@ -819,8 +819,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // coupling a_k, far coupling u_k), the upper lane towards nz-1 (near
     // u_k, far a_k).
     // FP64 streams in 4-level chunks: with 8 the half column's registers
-    // exceed 256 and the kernel drops to one wave per SIMD
-    constexpr int CHW = sizeof(T) == 8 ? 4 : 8;
+    // exceed 256 and the kernel drops to one wave per SIMD.  binary32 values
+    // are half the bytes per load, so it streams 16 levels ahead where the
+    // half column allows (more bytes in flight per wave)
+    constexpr int CHW = sizeof(T) == 8 ? 4 : (H % 16 == 0 ? 16 : 8);
     constexpr int CH = H < CHW ? H : CHW;
     constexpr int NCH = H / CH;
     static_assert(H % CH == 0, "chunks must tile the half column");
@@ -898,7 +900,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
                 ff = fk;
                 uu = far;
             }
-            const CT inv = CT(1) / mk;
+            // binary32 column solve: the hardware reciprocal (about 1 ulp;
+            // the preconditioner only has to be a fixed operator); FP64:
+            // the correctly rounded quotient
+            CT inv;
+            if constexpr (sizeof(CT) == 4) inv = __builtin_amdgcn_rcpf(mk);
+            else inv = CT(1) / mk;
             const CT g_new = far * inv;
             const CT d_new = fk * inv;
             if (mine) {
