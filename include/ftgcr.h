@@ -162,7 +162,7 @@ typedef struct {
 typedef struct ftgcr_handle ftgcr_handle;
 
 /* Fill *opt with defaults: ft=1, poll_steps=16, max_steps=100000,
- * inner_tol=1e-5, max_refinements=20, inner_max_steps=5000, hist_cap=65536,
+ * inner_tol=3e-5, max_refinements=20, inner_max_steps=5000, hist_cap=65536,
  * use_graphs=1, levels_per_block=0. */
 void ftgcr_default_options(ftgcr_options* opt);
 

@@ -442,7 +442,8 @@ struct Runner {
     ftgcr_status read_status(int* status)
     {
         HIP_TRY(h, hipGetLastError());
-        HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, offsetof(SolveState, s) + sizeof(long long),
+        // the status, the counters and the norms the next chunk is sized from
+        HIP_TRY(h, hipMemcpyAsync(h->st_host, h->st, offsetof(SolveState, rr_new) + sizeof(double),
                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
         collect_times(h, h->st_host->s);
@@ -458,6 +459,13 @@ struct Runner {
         const int chunk = std::max(1, h->opt.poll_steps);
         const long long guard = cap + chunk + 16;
         long long issued = 0;
+        // Chunks after the first are sized from the observed convergence
+        // rate: steps past the exit are launched and return at once, so the
+        // last chunk should end near it.  A rate estimate that is too short
+        // only costs one more status read.
+        long long want = chunk;
+        double rr_prev = -1.0;
+        long long s_prev = 0;
         while (true) {
             while (evp < evs.size() && evs[evp].step <= launched) ++evp;
             if (evp < evs.size() && evs[evp].step == launched + 1) {
@@ -470,7 +478,7 @@ struct Runner {
                 launched += 1;
                 issued += 1;
             } else {
-                long long cnt = chunk;
+                long long cnt = want;
                 if (evp < evs.size()) cnt = std::min<long long>(cnt, evs[evp].step - 1 - launched);
                 cnt = std::max<long long>(cnt, 1);
                 if (cnt == chunk && h->opt.use_graphs && !h->opt.profile_kernels) {
@@ -487,6 +495,18 @@ struct Runner {
             if (rc != FTGCR_OK) return rc;
             if (status != RUNNING) return FTGCR_OK;
             if (issued > guard) return fail(h, FTGCR_E_HIP, "step loop did not terminate");
+            const SolveState& hs = *h->st_host;
+            want = chunk;
+            if (rr_prev > 0.0 && hs.s > s_prev && hs.rr_old > hs.T && hs.rr_old < rr_prev) {
+                // per-step factor of <r, r> since the last read
+                const double rate = std::pow(hs.rr_old / rr_prev, 1.0 / (double)(hs.s - s_prev));
+                if (rate < 1.0 && rate > 0.0) {
+                    const double left = std::log(hs.T / hs.rr_old) / std::log(rate);
+                    if (left >= 0.0 && left < (double)chunk) want = std::max<long long>(1, (long long)std::ceil(left) + 1);
+                }
+            }
+            rr_prev = hs.rr_old;
+            s_prev = hs.s;
         }
     }
 };
@@ -916,7 +936,7 @@ void ftgcr_default_options(ftgcr_options* opt)
     opt->ft = 1;
     opt->poll_steps = 16;
     opt->max_steps = 100000;
-    opt->inner_tol = 1e-5;
+    opt->inner_tol = 3e-5;
     opt->max_refinements = 20;
     opt->inner_max_steps = 5000;
     opt->hist_cap = 65536;
