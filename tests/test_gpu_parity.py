@@ -416,3 +416,42 @@ def test_autotune_keeps_results(ft, oracle_mod):
     assert s.options()["levels_per_block"] == 0
     s.close()
     _solve_parity(ft, oracle_mod, pb, 3, rhs_seed=8)
+
+
+@pytest.mark.parametrize("shape,kc", [((70, 9, 33), 1), ((70, 9, 33), 16), ((64, 8, 96), 2), ((64, 8, 96), 8),
+                                      ((130, 5, 7), 4)])
+def test_solve_parity_across_tilings(ft, oracle_mod, shape, kc):
+    """Odd and maximal column heights (nz 33 and 96: half columns of 17 and
+    48 levels), ragged tiles in x and y, and every level tiling (the dots
+    pass at kc levels per block, the direction pass at min(kc, 4)), with a
+    fault in the run: the same decisions, x within 1e-10 at equal steps."""
+    _say("tiling", shape, kc)
+    pb = Problem(*shape, hill_lon=2.0, hill_amp=0.8)
+    rhs = I.rhs(pb, 31)
+    plan = [FaultEvent(7, "ap", 62, idx=np.arange(0, pb.n, 13))]
+    s = ft.Solver(pb, kmax=4, levels_per_block=kc)
+    x, st = s.solve(rhs, tol=1e-10, k=4, plan=plan)
+    s.close()
+    o = oracle_mod.Oracle(pb)
+    xo, so, logo, _ = o.solve(rhs, tol=1e-10, k=4, plan=plan)
+    assert _decisions(st["log"]) == _decisions(logo)
+    assert st["status"] == so["status"] == ft.CONVERGED
+    assert abs(st["steps_executed"] - so["steps_executed"]) <= 1
+    xe, _, _, _ = o.solve(rhs, tol=1e-13, k=4, plan=plan, max_steps=st["steps_executed"])
+    assert _rel(x.cpu().numpy(), xe) <= 1e-10
+
+
+@pytest.mark.parametrize("shape,kc", [((70, 9, 33), 16), ((64, 8, 96), 4)])
+def test_mixed_across_tilings(ft, oracle_mod, shape, kc):
+    """The mixed form on odd and maximal column heights (binary32 column
+    solve with 17- and 48-level half columns) and other tilings: the FP64
+    true residual meets the tolerance (oracle's operator)."""
+    _say("mixed tiling", shape, kc)
+    pb = Problem(*shape, hill_amp=0.5)
+    rhs = I.rhs(pb, 32)
+    s = ft.Solver(pb, "mixed", kmax=4, levels_per_block=kc)
+    x, st = s.solve(rhs, tol=1e-8, k=4)
+    s.close()
+    assert st["status"] == ft.CONVERGED
+    true = oracle_mod.Oracle(pb).true_residual(x.cpu().numpy(), rhs)
+    assert true <= 1.001e-8, true
