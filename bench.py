@@ -105,8 +105,9 @@ def main():
     torch.cuda.synchronize()
     print("[bench] fp64 warmup done", flush=True)
 
-    # per-kernel breakdown (one solve, every step kernel bracketed by HIP
-    # events), which also names the dominant kernel
+    # per-kernel breakdown (one solve, every step kernel's launch stamped
+    # with HIP start/stop events by its own dispatch), which also names the
+    # dominant kernel
     names = ("update_thomas", "stencil_dots", "dir_update")
     s64.set_options(profile_kernels=1)
     s64.reset_kernel_times()
@@ -117,9 +118,9 @@ def main():
     kernels = {q: {"launches": int(v[0]), "avg_us": (v[1] / v[0] * 1e3) if v[0] else 0.0} for q, v in kt_all.items()}
     dom = max(names, key=lambda q: kt_all[q][1])
 
-    # timed region: K whole solves; only the dominant kernel's launches are
-    # bracketed by HIP events (on the solve stream), so the events cost the
-    # whole-solve rate as little as possible
+    # timed region: K whole solves; only the dominant kernel's launches carry
+    # HIP start/stop events (stamped by the dispatch, on the solve stream), so
+    # the timing costs the whole-solve rate as little as possible
     s64.set_options(profile_kernels=2 << names.index(dom))
     s64.reset_kernel_times()
     torch.cuda.synchronize()

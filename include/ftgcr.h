@@ -87,8 +87,9 @@ typedef struct {
     int64_t hist_cap;        /* entries of the per-step residual history kept   */
     int32_t use_graphs;      /* 1: replay captured step sequences (hipGraph)     */
     int32_t levels_per_block;/* stencil kernels: levels per block (0 = auto)    */
-    int32_t profile_kernels; /* time step kernels with a HIP event pair each on
-                                the solve stream (ftgcr_kernel_times): 0 off,
+    int32_t profile_kernels; /* time step kernels with a HIP event pair each,
+                                stamped by the kernel's own dispatch on the
+                                solve stream (ftgcr_kernel_times): 0 off,
                                 1 all three, else a mask of bit 1
                                 update_thomas, bit 2 stencil_dots, bit 3
                                 dir_update                                      */
@@ -224,7 +225,8 @@ ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_sc
 
 /* Per-kernel device time accumulated while options.profile_kernels != 0:
  * one record per kernel of the step sequence (update_thomas, stencil_dots,
- * dir_update), each the sum of the HIP event intervals around its launches
+ * dir_update), each the sum of its launches' execution times (start and
+ * stop events stamped by each dispatch)
  * (launches enqueued after the solve ended are not counted).  Writes min(cap, count) records
  * and the count to *n_out. */
 typedef struct {

@@ -353,17 +353,17 @@ struct Runner {
         // dir_update)
         const int mask = h->opt.profile_kernels == 1 ? 0xE : h->opt.profile_kernels;
         if (!(mask & (2 << cls))) {
-            launch();
+            launch(nullptr, nullptr);
             return;
         }
         hipEvent_t a = take_event(h), b = take_event(h);
         if (!a || !b) {
-            launch();
+            launch(nullptr, nullptr);
             return;
         }
-        (void)hipEventRecord(a, s);
-        launch();
-        (void)hipEventRecord(b, s);
+        // the dispatch stamps a and b itself: the kernel's own execution
+        // time, with no event packets between it and its neighbours
+        launch(a, b);
         h->pending.push_back({cls, cur_step, a, b});
     }
 
@@ -399,13 +399,19 @@ struct Runner {
     void step(long long number, const std::vector<const DevEvent*>* mid = nullptr)
     {
         cur_step = number;
-        timed(0, [&] { L::update_thomas(tb, h->nblk_col, h->H, 0, s); });
-        L::finish_col(tb, 0, s);
-        if (mid)
+        timed(0, [&](hipEvent_t a, hipEvent_t b) { L::update_thomas(tb, h->nblk_col, h->H, 0, s, a, b); });
+        if (mid && !mid->empty()) {
+            // e events go between the decision and the dots pass
+            L::finish_col(tb, 0, s);
             for (const DevEvent* ev : *mid) event(*ev);
-        timed(1, [&] { L::stencil_dots(tb, h->nblk_st, h->kc, s); });
-        L::finish_alpha(tb, s);
-        timed(2, [&] { L::dir_update(tb, h->nblk_dir, h->kc_dir, 0, s); });
+            timed(1, [&](hipEvent_t a, hipEvent_t b) { L::stencil_dots(tb, h->nblk_st, h->kc, 0, s, a, b); });
+            L::finish_alpha(tb, s);
+        } else {
+            // dots pass first, then decision and alpha in one launch
+            timed(1, [&](hipEvent_t a, hipEvent_t b) { L::stencil_dots(tb, h->nblk_st, h->kc, 1, s, a, b); });
+            L::finish_step(tb, s);
+        }
+        timed(2, [&](hipEvent_t a, hipEvent_t b) { L::dir_update(tb, h->nblk_dir, h->kc_dir, 0, s, a, b); });
         L::finish_beta(tb, 0, s);
     }
 
@@ -855,10 +861,15 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
             if (evp[m] < evs[m].size()) cnt = std::min<long long>(cnt, std::max<long long>(1, evs[m][evp[m]].step - 1 - launched));
         for (long long q = 0; q < cnt; ++q) {
             L::update_thomas(tb, bt.cols, H, 0, s);
-            L::finish_col(tb, 0, s);
-            for (const auto& me : mid) apply(me.first, *me.second);   // cnt == 1 whenever mid is not empty
-            L::stencil_dots(tb, bt.sts, kc, s);
-            L::finish_alpha(tb, s);
+            if (!mid.empty()) {   // cnt == 1 whenever mid is not empty
+                L::finish_col(tb, 0, s);
+                for (const auto& me : mid) apply(me.first, *me.second);
+                L::stencil_dots(tb, bt.sts, kc, 0, s);
+                L::finish_alpha(tb, s);
+            } else {
+                L::stencil_dots(tb, bt.sts, kc, 1, s);
+                L::finish_step(tb, s);
+            }
             L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 0, s);
             L::finish_beta(tb, 0, s);
         }

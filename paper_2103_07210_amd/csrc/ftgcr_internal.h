@@ -17,6 +17,9 @@ namespace ftgcr {
 constexpr int KMAX = FTGCR_KMAX;
 constexpr int LOG_CAP = FTGCR_LOG_CAP;
 constexpr int NV_MAX = KMAX + 2;     // reduction values per block
+constexpr int DOT_ROW0 = 2;          // first partials row of the dots pass (rows 0, 1:
+                                     // the column pass's, still unread when a
+                                     // speculative dots pass runs)
 constexpr int RUNNING = -1;
 
 // Block shapes.  Column kernels: 256 threads = 4 waves, each wave owns 32
@@ -136,12 +139,19 @@ template <typename T> struct Launch {
                            int reset_counters, int grid, hipStream_t s);
     static void set_round(const Table<T>& tb, double tol2, long long max_steps, hipStream_t s);
     static void residual(const Table<T>& tb, int total_st_blocks, int kc, int store, int set_T, hipStream_t s);
-    static void update_thomas(const Table<T>& tb, int total_col_blocks, int H, int mode, hipStream_t s);
+    // update_thomas, stencil_dots and dir_update take optional events that
+    // the dispatch itself stamps with its start and stop times
+    static void update_thomas(const Table<T>& tb, int total_col_blocks, int H, int mode, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
     static void finish_col(const Table<T>& tb, int mode, hipStream_t s);
-    static void stencil_dots(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
+    // spec = 1: before the step's decision, followed by finish_step
+    static void stencil_dots(const Table<T>& tb, int total_st_blocks, int kc, int spec, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+    static void finish_step(const Table<T>& tb, hipStream_t s);   // finish_col + finish_alpha
     static void finish_alpha(const Table<T>& tb, hipStream_t s);
     static void finish_beta(const Table<T>& tb, int init, hipStream_t s);
-    static void dir_update(const Table<T>& tb, int total_st_blocks, int kc, int init, hipStream_t s);
+    static void dir_update(const Table<T>& tb, int total_st_blocks, int kc, int init, hipStream_t s,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
     static void finalize_x(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
     // fault events (single instance)
     static void event_prep(const Table<T>& tb, int vec, hipStream_t s);

@@ -24,6 +24,8 @@
 //
 // Storage type T is double (FP64 solve) or float (mixed precision: binary32
 // vectors, FP64 arithmetic in registers, FP64 inner products and iterate).
+#include <hip/hip_ext.h>
+
 #include "ftgcr_internal.h"
 
 namespace ftgcr {
@@ -114,34 +116,51 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 }
 
 // Fixed-order sums of values 0..nv-1 over an instance's block partials
-// (value-major: a value's partials are contiguous), by one RED_THREADS block:
+// (value-major: a value's partials are contiguous, value q in row row0 + q),
+// by one RED_THREADS block:
 // thread t adds blocks t, t + RED_THREADS, ... in order, then the waves are
-// summed in a fixed order.  Every value's loads are independent, so each
-// pass over the blocks is one round trip for all values.  The returned LDS
+// summed in a fixed order.  Values are taken G at a time, and each thread
+// issues the loads of U of its blocks for all G values before the first add,
+// so up to G * U * RED_THREADS partials cost one round trip to memory; the
+// order of the additions is the same for every (G, U).  The returned LDS
 // array holds the nv sums; out, if not null, gets the first two of them in
 // registers.  Both are valid in every thread.
-template <typename T>
-__device__ __forceinline__ const double* sum_partials(const Inst<T>& in, int nblk, int nv, double* out)
+template <int G, int U, typename T>
+__device__ __forceinline__ const double* sum_partials(const Inst<T>& in, int nblk, int row0, int nv, double* out)
 {
     constexpr int NW = RED_THREADS / 64;
     __shared__ double sh[NV_MAX][NW];
     __shared__ double res[NV_MAX];
     const gptr<double> part = as_global(in.part);
     const long long stride = in.pstride;
-    double acc[NV_MAX];
-#pragma unroll
-    for (int q = 0; q < NV_MAX; ++q) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RED_THREADS) {
-#pragma unroll
-        for (int q = 0; q < NV_MAX; ++q)
-            if (q < nv) acc[q] += part[(long long)q * stride + b];
-    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int q0 = 0; q0 < nv; q0 += G) {
+        double acc[G];
 #pragma unroll
-    for (int q = 0; q < NV_MAX; ++q) {
-        if (q < nv) {
-            const double v = wave_sum(acc[q]);
-            if (lane == 0) sh[q][w] = v;
+        for (int g = 0; g < G; ++g) acc[g] = 0.0;
+        for (int b0 = threadIdx.x; b0 < nblk; b0 += U * RED_THREADS) {
+            double v[U][G];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = b0 + u * RED_THREADS;
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    v[u][g] = (b < nblk && q0 + g < nv) ? part[(long long)(row0 + q0 + g) * stride + b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b0 + u * RED_THREADS < nblk) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[g] += v[u][g];
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (q0 + g < nv) {
+                const double t = wave_sum(acc[g]);
+                if (lane == 0) sh[q0 + g][w] = t;
+            }
         }
     }
     __syncthreads();
@@ -573,7 +592,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_residual(Table<T> tb, in
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
     double v[2];
-    sum_partials(in, in.nblk_st, 2, v);
+    sum_partials<2, 8>(in, in.nblk_st, 0, 2, v);
     const double RR = v[0], rt2 = v[1];
     if (threadIdx.x == 0) {
         st->RR = RR;
@@ -956,7 +975,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mod
     SolveState* st = in.st;
     if (st->status != RUNNING) return;
     double v[2];
-    sum_partials(in, in.nblk_col, 2, v);
+    sum_partials<2, 8>(in, in.nblk_col, 0, 2, v);
     const double rn = v[0], rs = v[1];
     if (threadIdx.x == 0) {
         if (mode == MODE_STEP) decide_step(st, rn, rs, in.hist, in.hist_cap);
@@ -968,8 +987,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mod
 // L(e) and orthogonalisation inner products (+ alpha)
 // ---------------------------------------------------------------------------
 
+// spec = 1: launched before the step's decision (k_finish_step takes it
+// afterwards); it runs whenever the column pass ran, and its partials are
+// discarded if the step is rejected or ends the solve.  Nothing it reads
+// (nu, the slots, e, the L(p^l)) is changed by the decision.
 template <typename T, int KC>
-__global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
+__global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb, int spec)
 {
     __shared__ double sh[KMAX + 1][4];
     __shared__ const T* s_ap[KMAX + 1];
@@ -977,7 +1000,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
     SolveState* st = in.st;
-    if (st->status != RUNNING || !st->active) return;
+    if (st->status != RUNNING || (spec ? st->d_cur == 0.0 : !st->active)) return;
     const int nu = st->nu;
     if ((int)threadIdx.x <= nu) s_ap[threadIdx.x] = in.AP[st->slot[threadIdx.x]];
     __syncthreads();
@@ -990,7 +1013,6 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
         if (!(ps.col_ok && ps.k0 + kk < nz)) le[kk] = 0.0;
-    // every <L(e), L(p^l)>: one uniform branch per l, its KC loads batched
     // every <L(e), L(p^l)>, one uniform branch per l; the loads of term
     // l + 1 are issued before term l's values are used (a two-stage
     // pipeline), so the terms cost one memory round trip together, not one
@@ -1038,8 +1060,19 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb)
     __syncthreads();
     if ((int)threadIdx.x <= nu) {
         const int l = threadIdx.x;
-        in.part[(long long)(l) * in.pstride + lb] = ((sh[l][0] + sh[l][1]) + sh[l][2]) + sh[l][3];
+        in.part[(long long)(DOT_ROW0 + l) * in.pstride + lb] = ((sh[l][0] + sh[l][1]) + sh[l][2]) + sh[l][3];
     }
+}
+
+// alpha_l = -<L(e), L(p^l)> / <L(p^l), L(p^l)> and the iterate buffer the
+// direction pass writes; every thread of the block calls it.
+template <typename T>
+__device__ __forceinline__ void finish_alpha_body(const Inst<T>& in, SolveState* st)
+{
+    const int nu = st->nu;
+    const double* v = sum_partials<4, 4>(in, in.nblk_st, DOT_ROW0, nu + 1, nullptr);
+    if ((int)threadIdx.x <= nu) st->alpha[threadIdx.x] = -v[threadIdx.x] / st->d[threadIdx.x];
+    if (threadIdx.x == 0) st->x_dst = (st->x_base == st->x_bak) ? 1 - st->x_base : st->x_base;
 }
 
 template <typename T>
@@ -1048,10 +1081,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(Table<T> tb)
     const Inst<T>& in = tb.inst[blockIdx.x];
     SolveState* st = in.st;
     if (st->status != RUNNING || !st->active) return;
-    const int nu = st->nu;
-    const double* v = sum_partials(in, in.nblk_st, nu + 1, nullptr);
-    if ((int)threadIdx.x <= nu) st->alpha[threadIdx.x] = -v[threadIdx.x] / st->d[threadIdx.x];
-    if (threadIdx.x == 0) st->x_dst = (st->x_base == st->x_bak) ? 1 - st->x_base : st->x_base;
+    finish_alpha_body(in, st);
+}
+
+// The step's decision (k_finish_col) and, if the step goes on, its alpha
+// (k_finish_alpha) in one launch, after a speculative dots pass.
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_finish_step(Table<T> tb)
+{
+    const Inst<T>& in = tb.inst[blockIdx.x];
+    SolveState* st = in.st;
+    if (st->status != RUNNING) return;
+    double v[2];
+    sum_partials<2, 8>(in, in.nblk_col, 0, 2, v);
+    if (threadIdx.x == 0) decide_step(st, v[0], v[1], in.hist, in.hist_cap);
+    __syncthreads();
+    if (st->status != RUNNING || !st->active) return;
+    finish_alpha_body(in, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1172,7 +1218,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int in
     if (st->status != RUNNING) return;
     if (!init && !st->active) return;
     double v[2];
-    sum_partials(in, in.nblk_dir, 2, v);
+    sum_partials<2, 8>(in, in.nblk_dir, 0, 2, v);
     const double num = v[0], dn = v[1];
     if (threadIdx.x == 0) decide_beta(st, num, dn, init);
 }
@@ -1344,7 +1390,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta_dots(Table<T> tb)
     SolveState* st = in.st;
     if (!st->ev_ok) return;
     double v[2];
-    sum_partials(in, in.nblk_st, 2, v);
+    sum_partials<2, 8>(in, in.nblk_st, 0, 2, v);
     const double num = v[0], dn = v[1];
     if (threadIdx.x == 0) {
         st->beta_num = num;
@@ -1382,6 +1428,16 @@ __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, 
     case 8: { constexpr int KCV = 8; CALL; } break;       \
     default: { constexpr int KCV = 16; CALL; } break;     \
     }
+
+// A launch whose start and stop times, if events are given, are taken by
+// the dispatch itself (no separate event packets on the stream).
+#define FTGCR_TIMED_LAUNCH(E0, E1, KERNEL, GRID, BLOCK, S, ...)                       \
+    do {                                                                              \
+        if (E0)                                                                       \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, S, E0, E1, 0, __VA_ARGS__); \
+        else                                                                          \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, S, __VA_ARGS__);               \
+    } while (0)
 
 #define FTGCR_H_SWITCH(H, CALL)                           \
     switch (H) {                                          \
@@ -1424,11 +1480,12 @@ void Launch<T>::residual(const Table<T>& tb, int total, int kc, int store, int s
 }
 
 template <typename T>
-void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hipStream_t s)
+void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1)
 {
     if (mode == MODE_STEP)
-        FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV, MODE_STEP>), dim3(total), dim3(COL_THREADS), 0,
-                                             s, tb, (const T*)nullptr, (T*)nullptr))
+        FTGCR_H_SWITCH(H, FTGCR_TIMED_LAUNCH(e0, e1, (k_update_thomas<T, HV, MODE_STEP>), dim3(total),
+                                             dim3(COL_THREADS), s, tb, (const T*)nullptr, (T*)nullptr))
     else
         FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV, MODE_INIT>), dim3(total), dim3(COL_THREADS), 0,
                                              s, tb, (const T*)nullptr, (T*)nullptr))
@@ -1453,15 +1510,25 @@ void Launch<T>::finish_beta(const Table<T>& tb, int init, hipStream_t s)
 }
 
 template <typename T>
-void Launch<T>::stencil_dots(const Table<T>& tb, int total, int kc, hipStream_t s)
+void Launch<T>::stencil_dots(const Table<T>& tb, int total, int kc, int spec, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_stencil_dots<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb));
+    FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_stencil_dots<T, KCV>), dim3(total), dim3(ST_THREADS), s, tb,
+                                           spec));
 }
 
 template <typename T>
-void Launch<T>::dir_update(const Table<T>& tb, int total, int kc, int init, hipStream_t s)
+void Launch<T>::finish_step(const Table<T>& tb, hipStream_t s)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_dir_update<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb, init));
+    hipLaunchKernelGGL(k_finish_step<T>, dim3(tb.n), dim3(RED_THREADS), 0, s, tb);
+}
+
+template <typename T>
+void Launch<T>::dir_update(const Table<T>& tb, int total, int kc, int init, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1)
+{
+    FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV>), dim3(total), dim3(ST_THREADS), s, tb,
+                                           init));
 }
 
 template <typename T>
