@@ -227,6 +227,8 @@ def main():
         solvers = [ftgcr.Solver(mb.problem, "fp64", kmax=3, poll_steps=32) for mb in members]
         erhs = [torch.from_numpy(I.rhs(mb.problem, mb.rhs_seed)).cuda() for mb in members]
         plans = [mb.plan for mb in members]
+        batch_kc = ftgcr.autotune_batch(solvers, erhs, k=3, steps=24)
+        print(f"[bench] ensemble tiling: {batch_kc} levels per block", flush=True)
         ftgcr.solve_batch(solvers, erhs, tols=[1e-10] * 64, k=3, plans=plans)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -240,7 +242,7 @@ def main():
         seq_ms = (time.perf_counter() - t1) * 1e3
         steps_all = sum(b["steps_executed"] for b in bst)
         points = sum(mb.problem.n for mb in members)
-        ensemble = {"members": 64, "points": points, "k": 3, "tol": 1e-10,
+        ensemble = {"members": 64, "points": points, "k": 3, "tol": 1e-10, "levels_per_block": batch_kc,
                     "batched_ms": batched_ms, "sequential_ms": seq_ms,
                     "member_steps_total": steps_all, "member_steps_per_s_batched": steps_all / batched_ms * 1e3,
                     "all_converged": all(b["status"] == 0 for b in bst),

@@ -93,7 +93,11 @@ typedef struct {
                                 1 all three, else a mask of bit 1
                                 update_thomas, bit 2 stencil_dots, bit 3
                                 dir_update                                      */
-    int32_t pad_;
+    int32_t batch_levels_per_block; /* ftgcr_solve_batch with this handle as
+                                the first member: stencil levels per block of
+                                the combined launches (1, 2, 4, 8 or 16; 0 =
+                                the largest member's own tiling); set by
+                                ftgcr_autotune_batch                            */
 } ftgcr_options;
 
 /* Fault injection (test harness).  XOR bit `bit` (or bits[t] per entry) into
@@ -214,6 +218,17 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n,
                                const double* const* rhs, double* const* x,
                                const double* tol, int32_t k,
                                const ftgcr_fault_plan* plans, ftgcr_stats* stats);
+
+/* Tiling autotune of a batch (the ensemble's launch shape): times `steps`
+ * batched steps of these members (fault-free, from x = 0) at 2, 4 and 8
+ * stencil levels per block (those not above the deepest member's nz), keeps
+ * the fastest in hs[0]'s options.batch_levels_per_block and writes it to
+ * *chosen (optional).  Arguments as in ftgcr_solve_batch; x_scratch[m] is an
+ * FP64 device buffer of member m's N entries, overwritten.  Every member's
+ * other options are as before on return, also on error. */
+ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n,
+                                  const double* const* rhs, double* const* x_scratch,
+                                  int32_t k, int32_t steps, int32_t* chosen);
 
 /* Autotuner of the stencil tiling (levels of a column per block): times
  * `steps` steps of this problem for each candidate and keeps the fastest for

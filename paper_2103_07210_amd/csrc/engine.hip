@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -733,8 +734,9 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     using L = Launch<double>;
     ftgcr_handle* h0 = hs[0];
     hipStream_t s = h0->stream;
-    // common tiling: Thomas depth of the deepest member, stencil levels per
-    // block chosen for the largest member
+    // common tiling: Thomas depth of the deepest member; stencil levels per
+    // block from the first member's batch option (ftgcr_autotune_batch), else
+    // those of the largest member
     int H = 4, kc = 1;
     long long biggest = -1;
     for (int m = 0; m < n; ++m) {
@@ -744,6 +746,8 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
             kc = hs[m]->kc;
         }
     }
+    const int bkc = h0->opt.batch_levels_per_block;
+    if (bkc == 1 || bkc == 2 || bkc == 4 || bkc == 8 || bkc == 16) kc = bkc;
     std::vector<Inst<double>> ins(n);
     std::vector<std::vector<DevEvent>> evs(n);
     for (int m = 0; m < n; ++m) {
@@ -1151,6 +1155,69 @@ ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_sc
     ftgcr_status rc = upload_debug_inst(h);
     if (rc != FTGCR_OK) return rc;
     if (chosen) *chosen = h->kc;
+    return FTGCR_OK;
+}
+
+ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n, const double* const* rhs,
+                                  double* const* x_scratch, int32_t k, int32_t steps, int32_t* chosen)
+{
+    if (!hs || n < 1 || !rhs || !x_scratch || steps < 1) return FTGCR_E_INVALID;
+    for (int m = 0; m < n; ++m)
+        if (!hs[m] || !x_scratch[m]) return FTGCR_E_INVALID;
+    HIP_TRY(hs[0], hipSetDevice(hs[0]->device));
+    int nz_max = 1;
+    for (int m = 0; m < n; ++m) nz_max = std::max(nz_max, hs[m]->geo.nz);
+    std::vector<ftgcr_options> saved(n);
+    for (int m = 0; m < n; ++m) saved[m] = hs[m]->opt;
+    auto restore = [&]() {
+        for (int m = 0; m < n; ++m) (void)ftgcr_set_options(hs[m], &saved[m]);
+    };
+    for (int m = 0; m < n; ++m) {
+        ftgcr_options o = saved[m];
+        o.max_steps = steps;
+        o.profile_kernels = 0;
+        ftgcr_status rc = ftgcr_set_options(hs[m], &o);
+        if (rc != FTGCR_OK) {
+            restore();
+            return rc;
+        }
+    }
+    const std::vector<double> tol(n, 1e-300);   // never met: every member runs `steps` steps
+    int best = 0;
+    double best_ms = 0.0;
+    const int cand[] = {2, 4, 8};
+    for (int kc : cand) {
+        if (kc > nz_max && kc != cand[0]) continue;
+        hs[0]->opt.batch_levels_per_block = kc;
+        double ms_min = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+            for (int m = 0; m < n; ++m) {
+                const hipError_t e = hipMemsetAsync(x_scratch[m], 0, (size_t)hs[m]->geo.n * sizeof(double),
+                                                    hs[0]->stream);
+                if (e != hipSuccess) {
+                    restore();
+                    return fail(hs[0], FTGCR_E_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+                }
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            const ftgcr_status rc = ftgcr_solve_batch(hs, n, rhs, x_scratch, tol.data(), k, nullptr, nullptr);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rc != FTGCR_OK) {
+                const std::string err = hs[0]->err;
+                restore();
+                hs[0]->err = err;
+                return rc;
+            }
+            if (rep == 0 || ms < ms_min) ms_min = ms;
+        }
+        if (best == 0 || ms_min < best_ms) {
+            best = kc;
+            best_ms = ms_min;
+        }
+    }
+    restore();
+    hs[0]->opt.batch_levels_per_block = best;
+    if (chosen) *chosen = best;
     return FTGCR_OK;
 }
 

@@ -27,7 +27,8 @@ LOG_CAP = 256
 EXPORTED = ["ftgcr_default_options", "ftgcr_create", "ftgcr_set_options", "ftgcr_get_options",
             "ftgcr_set_stream", "ftgcr_workspace_bytes", "ftgcr_set_workspace", "ftgcr_solve",
             "ftgcr_solve_batch", "ftgcr_destroy", "ftgcr_last_error", "ftgcr_debug_apply_A",
-            "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times", "ftgcr_autotune"]
+            "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times", "ftgcr_autotune",
+            "ftgcr_autotune_batch"]
 
 
 class FtgcrError(RuntimeError):
@@ -53,7 +54,7 @@ class Options(ctypes.Structure):
                 ("max_refinements", ctypes.c_int32), ("inner_max_steps", ctypes.c_int32),
                 ("hist_cap", ctypes.c_int64), ("use_graphs", ctypes.c_int32),
                 ("levels_per_block", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("batch_levels_per_block", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -137,6 +138,9 @@ def load():
     lib.ftgcr_reset_kernel_times.restype = ctypes.c_int
     lib.ftgcr_autotune.argtypes = [H, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.ftgcr_autotune.restype = ctypes.c_int
+    lib.ftgcr_autotune_batch.argtypes = [ctypes.POINTER(H), ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.ftgcr_autotune_batch.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -360,3 +364,21 @@ def solve_batch(solvers: Sequence[Solver], rhs: Sequence, xs: Optional[Sequence]
         S[m].log = ctypes.cast(logs[m], ctypes.POINTER(DetectRec))
     _check(lib.ftgcr_solve_batch(H, n, R, X, T, int(k), P if plans else None, S), solvers[0]._h)
     return xs_t, [_stats_out(S[m], logs[m], None) for m in range(n)]
+
+
+def autotune_batch(solvers: Sequence[Solver], rhs: Sequence, k: int = 3, steps: int = 24) -> int:
+    """Time `steps` batched steps of these members per stencil tiling and
+    keep the fastest for later solve_batch calls led by solvers[0].  Returns
+    the chosen levels per block."""
+    import torch
+    lib = load()
+    n = len(solvers)
+    rhs_t = [s._dev(r) for s, r in zip(solvers, rhs)]
+    scratch = [torch.empty_like(r) for r in rhs_t]
+    H = (ctypes.c_void_p * n)(*[s._h for s in solvers])
+    R = (ctypes.c_void_p * n)(*[t.data_ptr() for t in rhs_t])
+    X = (ctypes.c_void_p * n)(*[t.data_ptr() for t in scratch])
+    chosen = ctypes.c_int32()
+    _check(lib.ftgcr_autotune_batch(H, n, R, X, int(k), int(steps), ctypes.byref(chosen)), solvers[0]._h)
+    torch.cuda.synchronize()
+    return chosen.value

@@ -343,6 +343,39 @@ def test_batch_matches_oracle_per_member(ft, oracle_mod):
         s.close()
 
 
+def test_batch_autotune_keeps_results(ft, oracle_mod):
+    """The batch tiling autotuner picks 2, 4 or 8 levels per block for the
+    combined launches, records it on the first member only, leaves every
+    member's other options as they were, and a batch at the chosen tiling
+    (with a fault in one member) still takes the oracle's decisions with x
+    within 1e-10 at equal step counts."""
+    pbs = [Problem(64, 32, 8), Problem(48, 24, 6, hill_lon=1.0), Problem(100, 7, 5), Problem(96, 48, 12)]
+    rhs = [I.rhs(pb, 70 + m) for m, pb in enumerate(pbs)]
+    plans = [[], [FaultEvent(5, "r", 62, idx=np.array([11]))], [], []]
+    solvers = [ft.Solver(pb, kmax=3) for pb in pbs]
+    before = [s.options() for s in solvers]
+    _say("batch autotune")
+    kc = ft.autotune_batch(solvers, rhs, k=3, steps=8)
+    assert kc in (2, 4, 8)
+    after = [s.options() for s in solvers]
+    assert after[0]["batch_levels_per_block"] == kc
+    for m, (b, a) in enumerate(zip(before, after)):
+        for key in b:
+            if not (m == 0 and key == "batch_levels_per_block"):
+                assert a[key] == b[key], (m, key)
+    xs, sts = ft.solve_batch(solvers, rhs, tols=[1e-10] * 4, k=3, plans=plans)
+    for m, pb in enumerate(pbs):
+        o = oracle_mod.Oracle(pb)
+        xo, so, logo, _ = o.solve(rhs[m], tol=1e-10, k=3, plan=plans[m])
+        assert sts[m]["status"] == ft.CONVERGED, m
+        assert _decisions(sts[m]["log"]) == _decisions(logo), m
+        assert abs(sts[m]["steps_executed"] - so["steps_executed"]) <= 1, m
+        xe, _, _, _ = o.solve(rhs[m], tol=1e-13, k=3, plan=plans[m], max_steps=sts[m]["steps_executed"])
+        assert _rel(xs[m].cpu().numpy(), xe) <= 1e-10, m
+    for s in solvers:
+        s.close()
+
+
 def test_batch_ensemble_workload(ft, oracle_mod):
     """The 64-member ensemble (sizes drawn from 64x32x8 .. 256x128x32, hill
     centre and amplitude per member, 6 members with one bit-62 flip in r):
