@@ -26,6 +26,8 @@
 // vectors, FP64 arithmetic in registers, FP64 inner products and iterate).
 #include <hip/hip_ext.h>
 
+#include <cstddef>
+
 #include "ftgcr_internal.h"
 
 namespace ftgcr {
@@ -605,6 +607,35 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_residual(Table<T> tb, in
 // decisions (single thread of the last block)
 // ---------------------------------------------------------------------------
 
+// The control state staged in LDS for a reduction block.  Every field read
+// by the decision logic would otherwise be a dependent round trip to memory
+// (and a read after a store to another field of the same type must go
+// back to memory); instead each of the first ST_WORDS threads loads one
+// 8-byte word of the state (all fields before the detection log) together
+// with the block's other loads, the decision runs on the LDS copy, and the
+// words are stored back once.  Barriers separate the word-wise copies from
+// the field accesses.
+constexpr int ST_WORDS = (int)(offsetof(SolveState, log) / 8);
+static_assert(offsetof(SolveState, log) % 8 == 0, "state words");
+static_assert(ST_WORDS <= RED_THREADS, "one word per thread");
+
+__device__ __forceinline__ long long state_word_load(const SolveState* g)
+{
+    const gptr<long long> w = as_global(reinterpret_cast<const long long*>(g));
+    return ((int)threadIdx.x < ST_WORDS) ? w[threadIdx.x] : 0;
+}
+
+__device__ __forceinline__ void state_word_stage(SolveState* s, long long w)
+{
+    if ((int)threadIdx.x < ST_WORDS) reinterpret_cast<long long*>(s)[threadIdx.x] = w;
+}
+
+__device__ __forceinline__ void state_word_store(SolveState* g, const SolveState* s)
+{
+    if ((int)threadIdx.x < ST_WORDS)
+        as_global_mut(reinterpret_cast<long long*>(g))[threadIdx.x] = reinterpret_cast<const long long*>(s)[threadIdx.x];
+}
+
 __device__ void rollback(SolveState* st)
 {
     st->slot[0] = st->b_slot0;
@@ -642,7 +673,10 @@ __device__ void decide_init(SolveState* st, double rn, double rs)
 // fault test with rollback to the backup, else (first pass of a cycle) the
 // new backup.  rn: <r+, r+> of the unrounded update (detector), rs: of the
 // stored r+ (exit test and next reference); equal in FP64.
-__device__ void decide_step(SolveState* st, double rn, double rs, double* hist, long long hist_cap)
+// `log` is the state's detection log (st itself may be a staged copy
+// without one).
+__device__ void decide_step(SolveState* st, DetectRec* log, double rn, double rs, double* hist,
+                            long long hist_cap)
 {
     const int nu = st->nu;
     st->s += 1;
@@ -672,7 +706,7 @@ __device__ void decide_step(SolveState* st, double rn, double rs, double* hist, 
         const int stag = (pos == st->last_rb_pos) && !st->events_since_rb;
         st->detections += 1;
         if (st->log_len < LOG_CAP) {
-            DetectRec& rec = st->log[st->log_len++];
+            DetectRec& rec = log[st->log_len++];
             rec.step = s;
             rec.nu = nu;
             rec.action = stag;
@@ -978,7 +1012,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mod
     sum_partials<2, 8>(in, in.nblk_col, 0, 2, v);
     const double rn = v[0], rs = v[1];
     if (threadIdx.x == 0) {
-        if (mode == MODE_STEP) decide_step(st, rn, rs, in.hist, in.hist_cap);
+        if (mode == MODE_STEP) decide_step(st, st->log, rn, rs, in.hist, in.hist_cap);
         else decide_init(st, rn, rs);
     }
 }
@@ -1089,15 +1123,24 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_alpha(Table<T> tb)
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_step(Table<T> tb)
 {
+    __shared__ SolveState s_st;
     const Inst<T>& in = tb.inst[blockIdx.x];
-    SolveState* st = in.st;
-    if (st->status != RUNNING) return;
+    SolveState* gst = in.st;
+    // the state's words and the column pass's partials in one round trip
+    // (the partials of a solve that is no longer running are read and
+    // ignored)
+    const long long word = state_word_load(gst);
     double v[2];
     sum_partials<2, 8>(in, in.nblk_col, 0, 2, v);
-    if (threadIdx.x == 0) decide_step(st, v[0], v[1], in.hist, in.hist_cap);
+    state_word_stage(&s_st, word);
     __syncthreads();
-    if (st->status != RUNNING || !st->active) return;
-    finish_alpha_body(in, st);
+    SolveState* st = &s_st;
+    if (st->status != RUNNING) return;
+    if (threadIdx.x == 0) decide_step(st, gst->log, v[0], v[1], in.hist, in.hist_cap);
+    __syncthreads();
+    if (st->status == RUNNING && st->active) finish_alpha_body(in, st);
+    __syncthreads();
+    state_word_store(gst, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1213,14 +1256,20 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int init)
 {
+    __shared__ SolveState s_st;
     const Inst<T>& in = tb.inst[blockIdx.x];
-    SolveState* st = in.st;
-    if (st->status != RUNNING) return;
-    if (!init && !st->active) return;
+    SolveState* gst = in.st;
+    const long long word = state_word_load(gst);
     double v[2];
     sum_partials<2, 8>(in, in.nblk_dir, 0, 2, v);
-    const double num = v[0], dn = v[1];
-    if (threadIdx.x == 0) decide_beta(st, num, dn, init);
+    state_word_stage(&s_st, word);
+    __syncthreads();
+    SolveState* st = &s_st;
+    if (st->status != RUNNING) return;
+    if (!init && !st->active) return;
+    if (threadIdx.x == 0) decide_beta(st, v[0], v[1], init);
+    __syncthreads();
+    state_word_store(gst, st);
 }
 
 // x = x_base + sum_{l = x_base_nu .. x_final_hi} beta_l p^l, into X[0].
