@@ -1,17 +1,23 @@
 // FT-GCR device kernels for gfx950 (MI355X).
 //
 // One inner step of Algorithm 1 (FT-GCR(k), arXiv 2103.07210) runs as three
-// streaming passes over HBM, each followed by a one-block reduction:
+// streaming passes over HBM and two one-block reductions:
 //
 //   update_thomas   r+ = r + beta L(p^nu), <r+, r+> partials, e = P^{-1} r+
-//     finish_col    exit test, monotone-norm fault test, backup or rollback
-//                   (Algorithm 1, red part)
 //   stencil_dots    L(e) and the partials of <L(e), L(p^l)>, l = 0..nu
-//     finish_alpha  alpha_l = -<L(e), L(p^l)> / <L(p^l), L(p^l)>
+//                   (launched before the step's decision: it writes only
+//                   its partials and reads nothing the decision changes)
+//     finish_step   exit test, monotone-norm fault test, backup or rollback
+//                   (Algorithm 1, red part), then
+//                   alpha_l = -<L(e), L(p^l)> / <L(p^l), L(p^l)>
 //   dir_update      p^{nu+1}, L(p^{nu+1}) (L(e) recomputed), the next beta's
 //                   inner products, and at the end of a cycle the deferred
 //                   iterate update phi += sum_l beta_l p^l
 //     finish_beta   beta, pass and cycle bookkeeping
+//
+// A step with faults to inject into e takes the decision in a launch of its
+// own (finish_col) so the injection can follow it, then finish_alpha after
+// the dots pass: the same arithmetic in the same order.
 //
 // The reductions are separate launches on purpose: a grid-wide "last block
 // finishes" scheme needs a device-scope fence and a same-address atomic per
@@ -807,7 +813,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     SolveState* st = in.st;
     if (mode != MODE_DEBUG) {
         if (st->status != RUNNING) return;
-        if (mode == MODE_STEP && st->d_cur == 0.0) return;   // finish_col records the breakdown
+        if (mode == MODE_STEP && st->d_cur == 0.0) return;   // the decision records the breakdown
     }
     // everything read from the instance and the state is copied to registers
     // before the first store, so no later access can wait behind a store
