@@ -67,6 +67,8 @@ struct ftgcr_handle {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
+    bool graph_nt_ap = false;
+    bool nt_ap = false;   // this solve's L(p^l) load hint (nt_ap_hint)
 
     int nblk_col = 0, nblk_st = 0, nblk_dir = 0;
     int kc = 1, tx = 1, ty = 1, tz = 1, H = 4, kc_dir = 1, tz_dir = 1;
@@ -373,7 +375,7 @@ struct Runner {
     // handle: the per-solve data live in the device-side instance record).
     ftgcr_status replay(int n)
     {
-        if (!h->graph || h->graph_steps != n) {
+        if (!h->graph || h->graph_steps != n || h->graph_nt_ap != h->nt_ap) {
             if (h->graph) {
                 (void)hipGraphExecDestroy(h->graph);
                 h->graph = nullptr;
@@ -390,6 +392,7 @@ struct Runner {
                 return fail(h, FTGCR_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
             }
             h->graph_steps = n;
+            h->graph_nt_ap = h->nt_ap;
         }
         HIP_TRY(h, hipGraphLaunch(h->graph, s));
         return FTGCR_OK;
@@ -412,7 +415,7 @@ struct Runner {
             timed(1, [&](hipEvent_t a, hipEvent_t b) { L::stencil_dots(tb, h->nblk_st, h->kc, 1, s, a, b); });
             L::finish_step(tb, s);
         }
-        timed(2, [&](hipEvent_t a, hipEvent_t b) { L::dir_update(tb, h->nblk_dir, h->kc_dir, 0, s, a, b); });
+        timed(2, [&](hipEvent_t a, hipEvent_t b) { L::dir_update(tb, h->nblk_dir, h->kc_dir, 0, h->nt_ap, s, a, b); });
         L::finish_beta(tb, 0, s);
     }
 
@@ -420,7 +423,7 @@ struct Runner {
     {
         L::update_thomas(tb, h->nblk_col, h->H, 1, s);
         L::finish_col(tb, 1, s);
-        L::dir_update(tb, h->nblk_dir, h->kc_dir, 1, s);
+        L::dir_update(tb, h->nblk_dir, h->kc_dir, 1, h->nt_ap, s);
         L::finish_beta(tb, 1, s);
     }
 
@@ -619,6 +622,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     if (rc != FTGCR_OK) return rc;
 
     Inst<T> in = make_inst<T>(h, rhs, x);
+    h->nt_ap = nt_ap_hint(k, h->geo.n, (int)sizeof(T));
     HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1}, s};
@@ -828,7 +832,10 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     L::residual(tb, bt.sts, kc, 1, 1, s);
     L::update_thomas(tb, bt.cols, H, 1, s);
     L::finish_col(tb, 1, s);
-    L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 1, s);
+    long long n_total = 0;
+    for (int m = 0; m < n; ++m) n_total += hs[m]->geo.n;
+    const bool nt_ap = nt_ap_hint(k, n_total, (int)sizeof(double));
+    L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 1, nt_ap, s);
     L::finish_beta(tb, 1, s);
 
     const int chunk = std::max(1, h0->opt.poll_steps);
@@ -874,7 +881,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
                 L::stencil_dots(tb, bt.sts, kc, 1, s);
                 L::finish_step(tb, s);
             }
-            L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 0, s);
+            L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 0, nt_ap, s);
             L::finish_beta(tb, 0, s);
         }
         launched += cnt;

@@ -150,7 +150,8 @@ template <typename T> struct Launch {
     static void finish_step(const Table<T>& tb, hipStream_t s);   // finish_col + finish_alpha
     static void finish_alpha(const Table<T>& tb, hipStream_t s);
     static void finish_beta(const Table<T>& tb, int init, hipStream_t s);
-    static void dir_update(const Table<T>& tb, int total_st_blocks, int kc, int init, hipStream_t s,
+    // nt_ap: load the L(p^l) with the non-temporal hint (nt_ap_hint)
+    static void dir_update(const Table<T>& tb, int total_st_blocks, int kc, int init, bool nt_ap, hipStream_t s,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
     static void finalize_x(const Table<T>& tb, int total_st_blocks, int kc, hipStream_t s);
     // fault events (single instance)
@@ -167,5 +168,14 @@ template <typename T> struct Launch {
 
 // Smallest supported register-array depth H >= levels per column half.
 int thomas_depth(int nz);
+
+// Whether the direction pass should load the L(p^l) with the non-temporal
+// hint: when the k + 1 images of A p of all solves in flight (n_total
+// entries of elem bytes each) exceed most of the 256 MB Infinity Cache, so
+// the next dots pass would not find them there anyway.
+inline bool nt_ap_hint(int k, long long n_total, int elem)
+{
+    return (double)(k + 1) * (double)n_total * elem > 192.0 * 1024 * 1024;
+}
 
 }  // namespace ftgcr

@@ -877,6 +877,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // for both halves: the lower lane eliminates towards level 0 (near
     // coupling a_k, far coupling u_k), the upper lane towards nz-1 (near
     // u_k, far a_k).
+    // r is loaded with the non-temporal hint: this is its last use in the
+    // step (the direction pass reads r+), and the hint leaves the Infinity
+    // Cache to what the next passes re-read (e, r+, the L(p^l)).
     // FP64 streams in 4-level chunks: with 8 the half column's registers
     // exceed 256 and the kernel drops to one wave per SIMD.  binary32 values
     // are half the bytes per load, so it streams 16 levels ahead where the
@@ -901,7 +904,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
         int k = upper ? nz - 1 - t : t;
         k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
         const long long o = (long long)colc + plane * k;
-        bufr[0][t] = rin[o];
+        bufr[0][t] = __builtin_nontemporal_load(&rin[o]);
         bufa[0][t] = (mode == MODE_STEP) ? ap[o] : T(0);
     }
 #pragma unroll
@@ -918,7 +921,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
                 int k = upper ? nz - 1 - q : q;
                 k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
                 const long long o = (long long)colc + plane * k;
-                bufr[b ^ 1][t] = rin[o];
+                bufr[b ^ 1][t] = __builtin_nontemporal_load(&rin[o]);
                 bufa[b ^ 1][t] = (mode == MODE_STEP) ? ap[o] : T(0);
             }
         }
@@ -1153,7 +1156,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_step(Table<T> tb)
 // new direction, its image, next beta's inner products, deferred iterate
 // ---------------------------------------------------------------------------
 
-template <typename T, int KC>
+// Cache hints: the p^l, the iterate and the new p^{nu+1} are next touched
+// a whole step later (more than the Infinity Cache holds in between), so
+// they are loaded and stored with the non-temporal hint, leaving the cache
+// to e, r+ and L(p^{nu+1}), which the next passes read within the step.
+// NTAP extends the hint to the L(p^l) loads: set when the solve's k + 1
+// images of A p do not fit the cache anyway (otherwise the next dots pass
+// finds them there).
+template <typename T, int KC, bool NTAP>
 __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init)
 {
     __shared__ double sh[4];
@@ -1196,7 +1206,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
         const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
         const long long c = c0 + plane * kq;
         r[kk] = (double)rv[c];
-        xa[kk] = xupd ? xb[c] : 0.0;
+        xa[kk] = xupd ? __builtin_nontemporal_load(&xb[c]) : 0.0;
     }
     // sums over l in ascending order; term l + 1's loads are issued before
     // term l's values are used (two-stage pipeline, as in the dots pass)
@@ -1207,8 +1217,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-            pb[0][kk] = p0[c0 + plane * kq];
-            ab[0][kk] = ap0[c0 + plane * kq];
+            pb[0][kk] = __builtin_nontemporal_load(&p0[c0 + plane * kq]);
+            ab[0][kk] = NTAP ? __builtin_nontemporal_load(&ap0[c0 + plane * kq]) : ap0[c0 + plane * kq];
         }
     }
 #pragma unroll
@@ -1222,8 +1232,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
                     const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-                    pb[(l + 1) & 1][kk] = pn[c0 + plane * kq];
-                    ab[(l + 1) & 1][kk] = apn[c0 + plane * kq];
+                    pb[(l + 1) & 1][kk] = __builtin_nontemporal_load(&pn[c0 + plane * kq]);
+                    ab[(l + 1) & 1][kk] = NTAP ? __builtin_nontemporal_load(&apn[c0 + plane * kq])
+                                               : apn[c0 + plane * kq];
                 }
             }
 #pragma unroll
@@ -1242,9 +1253,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
         const T as_ = (T)a[kk];
         if (ok) {
             const long long c = c0 + plane * (ps.k0 + kk);
-            pout[c] = ps_;
+            __builtin_nontemporal_store(ps_, &pout[c]);
             apout[c] = as_;
-            if (xupd) xo[c] = xa[kk];
+            if (xupd) __builtin_nontemporal_store(xa[kk], &xo[c]);
         }
         const double ad = ok ? (double)as_ : 0.0;
         const double rd = ok ? r[kk] : 0.0;
@@ -1579,11 +1590,15 @@ void Launch<T>::finish_step(const Table<T>& tb, hipStream_t s)
 }
 
 template <typename T>
-void Launch<T>::dir_update(const Table<T>& tb, int total, int kc, int init, hipStream_t s, hipEvent_t e0,
-                           hipEvent_t e1)
+void Launch<T>::dir_update(const Table<T>& tb, int total, int kc, int init, bool nt_ap, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1)
 {
-    FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV>), dim3(total), dim3(ST_THREADS), s, tb,
-                                           init));
+    if (nt_ap)
+        FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, true>), dim3(total), dim3(ST_THREADS),
+                                               s, tb, init))
+    else
+        FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, false>), dim3(total),
+                                               dim3(ST_THREADS), s, tb, init))
 }
 
 template <typename T>
