@@ -154,7 +154,8 @@ void dir_tiling(int kc, int nz, int tx, int ty, int& kc_dir, int& tz_dir, int& n
 void set_tiling(ftgcr_handle* h)
 {
     const Geo& g = h->geo;
-    h->nblk_col = (g.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK;
+    const int cpb = col_block_cols(h->precision == FTGCR_MIXED ? 4 : 8, h->H);
+    h->nblk_col = (g.ncols + cpb - 1) / cpb;
     h->tx = (g.nx + ST_TX - 1) / ST_TX;
     h->ty = (g.ny + ST_TY - 1) / ST_TY;
     int kc = h->opt.levels_per_block;
@@ -1294,7 +1295,9 @@ ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, doubl
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
     Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
-    Launch<double>::debug_pinv(tb, h->nblk_col, h->H, in_dev, out_dev, h->stream);
+    // the FP64 two-lane kernel, whatever the handle's own column tiling
+    Launch<double>::debug_pinv(tb, (h->geo.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK, h->H, in_dev, out_dev,
+                               h->stream);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return FTGCR_OK;

@@ -26,6 +26,14 @@ constexpr int RUNNING = -1;
 // columns (lanes 0..31 the lower half of each column, 32..63 the upper half).
 constexpr int COL_THREADS = 256;
 constexpr int COLS_PER_BLOCK = 128;
+
+// Columns per block of the column pass: the binary32 form with half columns
+// of at most 32 levels uses one lane per column (k_update_thomas1), the
+// others two lanes per column.
+inline int col_block_cols(int elem_bytes, int H)
+{
+    return (elem_bytes == 4 && H <= 32) ? COL_THREADS : COLS_PER_BLOCK;
+}
 // Stencil kernels: 64 longitudes x 4 latitudes per block, KC levels each.
 constexpr int ST_TX = 64;
 constexpr int ST_TY = 4;

@@ -1011,6 +1011,151 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     }
 }
 
+// The binary32 column pass with one lane per column (256 columns per
+// block), for columns of at most NZ = 64 levels.  The two-lane kernel above
+// needs more registers per lane in binary32 than fit four waves per SIMD, so
+// its 4096 waves on 512 x 256 columns take 1.33 rounds of the chip at three
+// per SIMD; with one lane per column there are half as many waves, which fit
+// in one round at two per SIMD, and every load is a full 256-byte wave
+// segment.  Same update, norms, faces, diagonal and elimination as above
+// (the lower lane's order, extended to the whole column), so P is the same
+// fixed operator up to rounding.
+template <typename T, int NZ, int mode>
+__global__ __launch_bounds__(COL_THREADS) void k_update_thomas1(Table<T> tb)
+{
+    static_assert(sizeof(T) == 4 && NZ % 8 == 0, "binary32, whole chunks");
+    using CT = T;
+    __shared__ double sh[4];
+    __shared__ CT s_gc[NZ];
+    __shared__ CT s_gf[NZ + 1];
+    const int m = find_inst(tb.blk0_col, tb.n, blockIdx.x);
+    const Inst<T>& in = tb.inst[m];
+    const int lb = blockIdx.x - tb.blk0_col[m];
+    SolveState* st = in.st;
+    if (st->status != RUNNING) return;
+    if (mode == MODE_STEP && st->d_cur == 0.0) return;   // the decision records the breakdown
+    const Geo& g = in.g;
+    const int nx = g.nx, nz = g.nz, ncols = g.ncols;
+    for (int t = threadIdx.x; t < nz; t += blockDim.x) s_gc[t] = (CT)g.gc[t];
+    for (int t = threadIdx.x; t <= nz; t += blockDim.x) s_gf[t] = (CT)g.gf[t];
+    const CT opsig_c = (CT)g.opsig;
+    const T* rin = in.R[st->r_cur];
+    const T* ap = rin;
+    T* rout = nullptr;
+    double beta = 0.0;
+    if (mode == MODE_STEP) {
+        ap = in.AP[st->slot[st->nu]];
+        rout = in.R[st->r_dst];
+        beta = -st->beta_num / st->d_cur;
+    }
+    T* eout = in.E;
+    double* part = in.part;
+    const long long pstride = in.pstride;
+    __syncthreads();
+
+    const int col = lb * COL_THREADS + threadIdx.x;
+    const bool valid = col < ncols;
+    const int colc = valid ? col : 0;
+    const int j = colc / nx;
+    const int i = colc - j * nx;
+    const long long plane = (long long)ncols;
+    const RowC rcst = row_consts(col_weights(g, i, j));
+    const CT h0 = (CT)rcst.h0;
+    const CT h1 = (CT)rcst.h1;
+    const CT gz = (CT)rcst.gz, hc = (CT)rcst.hc;
+
+    // levels stream in 8-level chunks, each chunk's loads issued one chunk
+    // ahead (as in the two-lane kernel); r is read with the non-temporal
+    // hint (its last use in the step)
+    constexpr int CH = 8;
+    constexpr int NCH = NZ / CH;
+    T bufr[2][CH], bufa[2][CH];
+    CT de[NZ], ga[NZ];
+    double acc_new = 0.0, acc_st = 0.0;
+    CT carry_g = 0, carry_d = 0;
+    CT w_near = 0;   // face below level 0
+    gptr_mut<T> rw = as_global_mut(mode == MODE_STEP ? rout : eout) + (long long)colc;
+    asm volatile("" : "+v"(rw));
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+        const int k = t > nz - 1 ? nz - 1 : t;
+        const long long o = (long long)colc + plane * k;
+        bufr[0][t] = __builtin_nontemporal_load(&rin[o]);
+        bufa[0][t] = (mode == MODE_STEP) ? ap[o] : T(0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCH; ++cb) {
+        const int b = cb & 1;
+        __builtin_amdgcn_sched_barrier(0);
+        if (cb + 1 < NCH) {
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                int k = (cb + 1) * CH + t;
+                k = k > nz - 1 ? nz - 1 : k;
+                const long long o = (long long)colc + plane * k;
+                bufr[b ^ 1][t] = __builtin_nontemporal_load(&rin[o]);
+                bufa[b ^ 1][t] = (mode == MODE_STEP) ? ap[o] : T(0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            const int q = cb * CH + t;   // level
+            const bool mine = q < nz;
+            const int k = q > nz - 1 ? nz - 1 : q;
+            const double v = (mode == MODE_STEP) ? fma(beta, (double)bufa[b][t], (double)bufr[b][t])
+                                                 : (double)bufr[b][t];
+            const T sv = (T)v;
+            const double rp = (double)sv;
+            const CT rc = (CT)sv;
+            if (mine && valid) {
+                if (mode == MODE_STEP) *rw = sv;
+                acc_new = fma(v, v, acc_new);
+                acc_st = fma(rp, rp, acc_st);
+            }
+            rw += plane;
+            const int f = k + 1;
+            const CT gff = s_gf[f];
+            const CT w_far = (f > 0 && f < nz) ? gz * fma(hc, gff, CT(1)) : CT(0);
+            const CT wb = w_near, wa = w_far;
+            w_near = w_far;
+            const CT diag = opsig_c * ((fma(s_gc[k], h1, h0) + wb) + wa);
+            const CT near = -wb;
+            const CT far = -wa;
+            const CT mk = (q == 0) ? diag : diag - near * carry_g;
+            const CT fk = (q == 0) ? rc : rc - near * carry_d;
+            const CT inv = __builtin_amdgcn_rcpf(mk);
+            const CT g_new = far * inv;
+            const CT d_new = fk * inv;
+            if (mine) {
+                carry_g = g_new;
+                carry_d = d_new;
+            }
+            ga[q] = g_new;
+            de[q] = d_new;
+        }
+    }
+    // back-substitution from the top level down
+    CT xv = carry_d;
+    gptr_mut<T> ep = as_global_mut(eout) + (long long)colc + plane * (nz - 1);
+    asm volatile("" : "+v"(ep));
+    if (valid) *ep = (T)xv;
+    ep -= plane;
+#pragma unroll
+    for (int q = NZ - 2; q >= 0; --q) {
+        if (q < nz - 1) {
+            xv = de[q] - ga[q] * xv;
+            if (valid) *ep = (T)xv;
+            ep -= plane;
+        }
+    }
+    const double sn = block_sum(acc_new, sh);
+    const double ss = block_sum(acc_st, sh);
+    if (threadIdx.x == 0) {
+        part[(long long)(0) * pstride + lb] = sn;
+        part[(long long)(1) * pstride + lb] = ss;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mode)
 {
@@ -1549,6 +1694,26 @@ template <typename T>
 void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (col_block_cols((int)sizeof(T), H) == COL_THREADS) {
+            // one lane per column: NZ = 2H levels at most (H <= 32)
+#define FTGCR_T1(HH)                                                                                        \
+    if (mode == MODE_STEP)                                                                                  \
+        FTGCR_TIMED_LAUNCH(e0, e1, (k_update_thomas1<T, 2 * HH, MODE_STEP>), dim3(total), dim3(COL_THREADS), \
+                           s, tb);                                                                          \
+    else                                                                                                    \
+        hipLaunchKernelGGL((k_update_thomas1<T, 2 * HH, MODE_INIT>), dim3(total), dim3(COL_THREADS), 0, s, tb);
+            switch (H) {
+            case 4: FTGCR_T1(4) break;
+            case 8: FTGCR_T1(8) break;
+            case 16: FTGCR_T1(16) break;
+            case 24: FTGCR_T1(24) break;
+            default: FTGCR_T1(32) break;
+            }
+#undef FTGCR_T1
+            return;
+        }
+    }
     if (mode == MODE_STEP)
         FTGCR_H_SWITCH(H, FTGCR_TIMED_LAUNCH(e0, e1, (k_update_thomas<T, HV, MODE_STEP>), dim3(total),
                                              dim3(COL_THREADS), s, tb, (const T*)nullptr, (T*)nullptr))

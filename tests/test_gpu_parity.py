@@ -488,3 +488,23 @@ def test_mixed_across_tilings(ft, oracle_mod, shape, kc):
     assert st["status"] == ft.CONVERGED
     true = oracle_mod.Oracle(pb).true_residual(x.cpu().numpy(), rhs)
     assert true <= 1.001e-8, true
+
+
+@pytest.mark.parametrize("shape", [(128, 64, 16), (70, 9, 30), (64, 32, 8), (64, 8, 96)])
+def test_mixed_preconditioner_matches_fp64_step_counts(ft, shape):
+    """The binary32 column solve (one lane per column up to 64 levels, two
+    lanes beyond) applies the same P as the FP64 one up to binary32
+    rounding: the mixed form's inner step count stays within 10% of the FP64
+    solve's (a wrong P would still converge, but in many more steps)."""
+    _say("mixed step counts", shape)
+    pb = Problem(*shape, hill_amp=0.7)
+    rhs = I.rhs(pb, 33)
+    s64 = ft.Solver(pb, kmax=4)
+    _, st64 = s64.solve(rhs, tol=1e-8, k=4)
+    s64.close()
+    sm = ft.Solver(pb, "mixed", kmax=4)
+    _, stm = sm.solve(rhs, tol=1e-8, k=4)
+    sm.close()
+    assert st64["status"] == stm["status"] == ft.CONVERGED
+    assert stm["rel_res_true"] <= 1.001e-8
+    assert stm["steps_executed"] <= 1.10 * st64["steps_executed"] + 8, (stm["steps_executed"], st64["steps_executed"])
