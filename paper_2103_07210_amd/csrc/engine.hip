@@ -258,8 +258,14 @@ ftgcr_status upload_tables(ftgcr_handle* h)
         Gz[j] = std::cos(lat_c(j)) * dlon * dlat / dz;
     }
     for (int j = 1; j < ny; ++j) Gy[j] = std::cos(lat_s(j)) * dlon * dz / dlat;   // poles stay exactly 0
-    HIP_TRY(h, hipMalloc(&h->tables, total * sizeof(double)));
+    // binary32 copies of hx, hy, hc (rounded to nearest) after the FP64 tables
+    const size_t n32 = nhx + nhy + nhc;
+    std::vector<float> t32(n32);
+    for (size_t q = 0; q < n32; ++q) t32[q] = (float)t[q];
+    HIP_TRY(h, hipMalloc(&h->tables, total * sizeof(double) + n32 * sizeof(float)));
     HIP_TRY(h, hipMemcpy(h->tables, t.data(), total * sizeof(double), hipMemcpyHostToDevice));
+    float* tab32 = reinterpret_cast<float*>(h->tables + total);
+    HIP_TRY(h, hipMemcpy(tab32, t32.data(), n32 * sizeof(float), hipMemcpyHostToDevice));
     Geo& g = h->geo;
     g.nx = nx;
     g.ny = ny;
@@ -275,6 +281,9 @@ ftgcr_status upload_tables(ftgcr_handle* h)
     g.Gx = g.gf + (nz + 1);
     g.Gy = g.Gx + ny;
     g.Gz = g.Gy + (ny + 1);
+    g.hx32 = tab32;
+    g.hy32 = g.hx32 + nhx;
+    g.hc32 = g.hy32 + nhy;
     return FTGCR_OK;
 }
 

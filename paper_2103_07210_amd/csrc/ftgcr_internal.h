@@ -104,6 +104,11 @@ struct Geo {
     const double* Gx;        // [ny]        dlat dz / (cos(lat_j) dlon)
     const double* Gy;        // [ny+1]      cos(lat_{j-1/2}) dlon dz / dlat, 0 at poles
     const double* Gz;        // [ny]        cos(lat_j) dlon dlat / dz
+    // binary32 copies of the per-column hill tables, read by the binary32
+    // stencil and column solve (half the bytes of the FP64 ones)
+    const float* hx32;
+    const float* hy32;
+    const float* hc32;
 };
 
 // Everything one instance's kernels need (device copy per solve).

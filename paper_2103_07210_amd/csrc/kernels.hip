@@ -247,10 +247,10 @@ __device__ __forceinline__ double vface(const RowC& r, double gf, int f, int nz)
     return (f > 0 && f < nz) ? r.gz * fma(r.hc, gf, 1.0) : 0.0;
 }
 
-// The same constants rounded to binary32, for the stencil of the mixed
-// form (binary32 vectors): there L(e) is stored in binary32, so forming it
-// in binary32 arithmetic changes it by the order of that rounding, at half
-// the vector-ALU cost of FP64.
+// The same constants in binary32, for the stencil and column solve of the
+// mixed form (binary32 vectors): there L(e) is stored in binary32, so
+// forming it in binary32 arithmetic changes it by the order of that
+// rounding, at half the vector-ALU cost of FP64 (row_consts32 below).
 struct RowCf {
     float gx, gys, gyn, cw, ce, cs, cn, h0, h1, gz, hc;
 };
@@ -260,17 +260,44 @@ struct RowOf;
 template <>
 struct RowOf<double> {
     using type = RowC;
-    __device__ static RowC make(const RowC& r) { return r; }
 };
 template <>
 struct RowOf<float> {
     using type = RowCf;
-    __device__ static RowCf make(const RowC& r)
-    {
-        return RowCf{(float)r.gx, (float)r.gys, (float)r.gyn, (float)r.cw, (float)r.ce, (float)r.cs,
-                     (float)r.cn, (float)r.h0, (float)r.h1, (float)r.gz, (float)r.hc};
-    }
 };
+
+// The binary32 row constants straight from the binary32 hill tables (the
+// per-row metric factors rounded from FP64), in the same operation order as
+// row_consts: the binary32 stencil and column solve read half the table
+// bytes, and their diagonals agree with each other as the FP64 ones do.
+__device__ __forceinline__ RowCf row_consts32(const Geo& g, int i, int j)
+{
+    const int iw = (i == 0) ? g.nx - 1 : i - 1;
+    const float hw = g.hx32[(long long)j * g.nx + iw];
+    const float he = g.hx32[(long long)j * g.nx + i];
+    const float hs = g.hy32[(long long)j * g.nx + i];
+    const float hn = g.hy32[(long long)(j + 1) * g.nx + i];
+    RowCf r;
+    r.gx = (float)g.Gx[j];
+    r.gys = (float)g.Gy[j];
+    r.gyn = (float)g.Gy[j + 1];
+    r.cw = r.gx * hw;
+    r.ce = r.gx * he;
+    r.cs = r.gys * hs;
+    r.cn = r.gyn * hn;
+    r.h0 = ((r.gx + r.gx) + r.gys) + r.gyn;
+    r.h1 = ((r.gx * (hw + he) + r.gys * hs) + r.gyn * hn);
+    r.gz = (float)g.Gz[j];
+    r.hc = g.hc32[(long long)j * g.nx + i];
+    return r;
+}
+
+template <typename AT>
+__device__ __forceinline__ typename RowOf<AT>::type row_consts_for(const Geo& g, int i, int j)
+{
+    if constexpr (sizeof(AT) == 4) return row_consts32(g, i, j);
+    else return row_consts(col_weights(g, i, j));
+}
 
 __device__ __forceinline__ float vface(const RowCf& r, float gf, int f, int nz)
 {
@@ -334,7 +361,7 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
     static_assert(KC <= 32, "edge lanes");
     using AT = TI;   // arithmetic type: FP64 for FP64 vectors, binary32 for binary32
     __shared__ AT s_row[ST_TY][KC][ST_TX];
-    const typename RowOf<AT>::type rc = RowOf<AT>::make(row_consts(col_weights(g, i, j)));
+    const typename RowOf<AT>::type rc = row_consts_for<AT>(g, i, j);
     const int nz = g.nz, nx = g.nx;
     const long long plane = (long long)g.ncols;
     const int lane = threadIdx.x & (ST_TX - 1);
@@ -860,13 +887,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const int h = (nz + 1) >> 1;   // lower half: levels [0, h)
     const int nup = nz - h;        // upper half: levels [h, nz)
     const int nmine = upper ? nup : h;
-    const ColW c = col_weights(g, i, j);
     // diagonal h0 + g_k h1 + vertical faces, from the same per-column
-    // constants and in the same order as the stencil rows (identical in FP64)
-    const RowC rcst = row_consts(c);
-    const CT h0 = (CT)rcst.h0;
-    const CT h1 = (CT)rcst.h1;
-    const CT gz = (CT)rcst.gz, hc = (CT)rcst.hc;
+    // constants and in the same order as the stencil rows (identical)
+    const typename RowOf<CT>::type rcst = row_consts_for<CT>(g, i, j);
+    const CT h0 = rcst.h0;
+    const CT h1 = rcst.h1;
+    const CT gz = rcst.gz, hc = rcst.hc;
 
     // The half column streams in chunks of CH levels, each chunk's loads
     // issued one chunk ahead of its elimination (a two-stage software
@@ -1059,10 +1085,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas1(Table<T> tb)
     const int j = colc / nx;
     const int i = colc - j * nx;
     const long long plane = (long long)ncols;
-    const RowC rcst = row_consts(col_weights(g, i, j));
-    const CT h0 = (CT)rcst.h0;
-    const CT h1 = (CT)rcst.h1;
-    const CT gz = (CT)rcst.gz, hc = (CT)rcst.hc;
+    const RowCf rcst = row_consts32(g, i, j);
+    const CT h0 = rcst.h0;
+    const CT h1 = rcst.h1;
+    const CT gz = rcst.gz, hc = rcst.hc;
 
     // levels stream in 8-level chunks, each chunk's loads issued one chunk
     // ahead (as in the two-lane kernel); r is read with the non-temporal
