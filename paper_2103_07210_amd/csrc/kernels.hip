@@ -461,6 +461,14 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
     }
 }
 
+// Depth of the direction-term load pipeline of the direction pass: the
+// loads of term l + TERM_PIPE - 1 are issued before term l is used.
+// binary32 loads carry half the bytes and the binary32 kernel has registers
+// to spare, so it keeps one more term in flight (64.1 vs 65.2 us on
+// 512 x 256 x 64; three stages in FP64 would cost occupancy).
+template <typename T>
+constexpr int TERM_PIPE = sizeof(T) == 4 ? 3 : 2;
+
 // Stencil-grid coordinates of this thread: (i, j) clamped into the grid for
 // addressing, `col_ok` whether the thread owns a real column.
 struct StPos {
@@ -1235,31 +1243,38 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb, int sp
     // constant after unrolling: no register copies, so the wait for term l
     // comes after term l + 1's loads are issued)
     double acc[KMAX + 1];
-    T buf[2][KC];
-    {
-        const gptr<T> ap0 = as_global(s_ap[0]);
+    // PD - 1 terms in flight ahead of the one in use (a deeper pipeline
+    // costs this pass occupancy without a gain, measured in both forms)
+    constexpr int PD = 2;
+    T buf[PD][KC];
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-            buf[0][kk] = ap0[c0 + plane * kq];
+    for (int l0 = 0; l0 < PD - 1; ++l0) {
+        if (l0 == 0 || l0 <= nu) {   // nu >= 0 here
+            const gptr<T> apn = as_global(s_ap[l0]);
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                buf[l0][kk] = apn[c0 + plane * kq];
+            }
         }
     }
 #pragma unroll
     for (int l = 0; l <= KMAX; ++l) {
         acc[l] = 0.0;
         if (l <= nu) {
-            if (l < KMAX && l + 1 <= nu) {
-                const gptr<T> apn = as_global(s_ap[l + 1]);
+            const int ln = l + PD - 1;
+            if (ln <= KMAX && ln <= nu) {
+                const gptr<T> apn = as_global(s_ap[ln]);
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
                     const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-                    buf[(l + 1) & 1][kk] = apn[c0 + plane * kq];
+                    buf[ln % PD][kk] = apn[c0 + plane * kq];
                 }
             }
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
                 const bool ok = ps.col_ok && ps.k0 + kk < nz;
-                acc[l] = fma(le[kk], ok ? (double)buf[l & 1][kk] : 0.0, acc[l]);
+                acc[l] = fma(le[kk], ok ? (double)buf[l % PD][kk] : 0.0, acc[l]);
             }
         }
     }
@@ -1381,15 +1396,19 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
     }
     // sums over l in ascending order; term l + 1's loads are issued before
     // term l's values are used (two-stage pipeline, as in the dots pass)
-    T pb[2][KC], ab[2][KC];
-    if (nu >= 0) {
-        const gptr<T> p0 = as_global(s_p[0]);
-        const gptr<T> ap0 = as_global(s_ap[0]);
+    constexpr int PD = TERM_PIPE<T>;
+    T pb[PD][KC], ab[PD][KC];
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-            pb[0][kk] = __builtin_nontemporal_load(&p0[c0 + plane * kq]);
-            ab[0][kk] = NTAP ? __builtin_nontemporal_load(&ap0[c0 + plane * kq]) : ap0[c0 + plane * kq];
+    for (int l0 = 0; l0 < PD - 1; ++l0) {
+        if (l0 <= nu) {
+            const gptr<T> pn = as_global(s_p[l0]);
+            const gptr<T> apn = as_global(s_ap[l0]);
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                pb[l0][kk] = __builtin_nontemporal_load(&pn[c0 + plane * kq]);
+                ab[l0][kk] = NTAP ? __builtin_nontemporal_load(&apn[c0 + plane * kq]) : apn[c0 + plane * kq];
+            }
         }
     }
 #pragma unroll
@@ -1397,22 +1416,23 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
         if (l <= nu) {
             const double al = s_al[l];
             const double bl = s_be[l];
-            if (l + 1 < KMAX && l + 1 <= nu) {
-                const gptr<T> pn = as_global(s_p[l + 1]);
-                const gptr<T> apn = as_global(s_ap[l + 1]);
+            const int ln = l + PD - 1;
+            if (ln < KMAX && ln <= nu) {
+                const gptr<T> pn = as_global(s_p[ln]);
+                const gptr<T> apn = as_global(s_ap[ln]);
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
                     const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-                    pb[(l + 1) & 1][kk] = __builtin_nontemporal_load(&pn[c0 + plane * kq]);
-                    ab[(l + 1) & 1][kk] = NTAP ? __builtin_nontemporal_load(&apn[c0 + plane * kq])
-                                               : apn[c0 + plane * kq];
+                    pb[ln % PD][kk] = __builtin_nontemporal_load(&pn[c0 + plane * kq]);
+                    ab[ln % PD][kk] = NTAP ? __builtin_nontemporal_load(&apn[c0 + plane * kq])
+                                           : apn[c0 + plane * kq];
                 }
             }
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
-                p[kk] = fma(al, (double)pb[l & 1][kk], p[kk]);
-                a[kk] = fma(al, (double)ab[l & 1][kk], a[kk]);
-                if (xupd) xa[kk] = fma(bl, (double)pb[l & 1][kk], xa[kk]);
+                p[kk] = fma(al, (double)pb[l % PD][kk], p[kk]);
+                a[kk] = fma(al, (double)ab[l % PD][kk], a[kk]);
+                if (xupd) xa[kk] = fma(bl, (double)pb[l % PD][kk], xa[kk]);
             }
         }
     }
