@@ -78,8 +78,8 @@ def main():
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu, args.mixed_steps, args.no_ensemble, args.no_large = 1, 0, True, 0, True, True
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU sharding is a design only "
-                                   "(horizontal column blocks, see the design notes); run with --gpus 1"}))
+        print(json.dumps({"error": "the FT-GCR library runs on one GPU; sharding across GPUs (horizontal "
+                                   "blocks of whole columns) is not implemented; run with --gpus 1"}))
         sys.exit(2)
 
     import numpy as np

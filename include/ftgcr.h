@@ -47,7 +47,7 @@ typedef enum {
     FTGCR_E_HIP = -2,          /* HIP runtime error                              */
     FTGCR_E_NOMEM = -3,        /* device or host allocation failed               */
     FTGCR_E_WORKSPACE = -4,    /* no workspace, or smaller than required         */
-    FTGCR_E_UNSUPPORTED = -5   /* valid but outside what this build supports     */
+    FTGCR_E_UNSUPPORTED = -5   /* valid but outside what the library supports    */
 } ftgcr_status;
 
 typedef enum { FTGCR_FP64 = 0, FTGCR_MIXED = 1 } ftgcr_precision;
