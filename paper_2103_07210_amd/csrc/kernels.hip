@@ -342,8 +342,9 @@ __device__ __forceinline__ float lane_read(float v, int l)
 //                segment's two edge values (one of them the periodic wrap)
 //                come from one load instruction, lanes 0..KC-1 west and
 //                32..32+KC-1 east, broadcast by readlane;
-//   south/north  the adjacent rows' centre values through LDS; only the
-//                tile's first and last rows load a halo row;
+//   south/north  FP64: the adjacent rows' centre values through LDS, only
+//                the tile's first and last rows load a halo row; binary32:
+//                each row loads its own south and north rows;
 //   below/above  registers (each thread holds its KC levels and one more on
 //                either side).
 // All loads use clamped in-range addresses and are issued before the first
@@ -352,7 +353,7 @@ __device__ __forceinline__ float lane_read(float v, int l)
 // and carry weight 0.  Entries at levels >= nz or in clamped columns are
 // garbage and must be masked by the caller.  `centre`, if given, receives
 // x at the KC levels (as loaded).  Every thread of the block must call this
-// (it holds a barrier).
+// (the FP64 form holds a barrier).
 template <typename TI, int KC>
 __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict__ x, int i, int j,
                                               int k0, double (&out)[KC], double* centre = nullptr)
@@ -387,33 +388,49 @@ __device__ __forceinline__ void stencil_chunk(const Geo& g, const TI* __restrict
         k = k > nz - 1 ? nz - 1 : k;
         edge = (AT)x[row + plane * k + (lane < 32 ? iw0 : ie0)];
     }
-    // halo rows of the tile (first row: south, last row: north)
-    if (w == 0) {
-        const long long so = has_s ? -(long long)nx : 0;
+    if constexpr (sizeof(AT) == 8) {
+        // halo rows of the tile (first row: south, last row: north); the
+        // inner rows come from the adjacent waves through LDS
+        if (w == 0) {
+            const long long so = has_s ? -(long long)nx : 0;
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
-            xs[kk] = (AT)x[row + so + plane * k + i];
+            for (int kk = 0; kk < KC; ++kk) {
+                const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+                xs[kk] = (AT)x[row + so + plane * k + i];
+            }
         }
-    }
-    if (w == ST_TY - 1) {
+        if (w == ST_TY - 1) {
+            const long long no = has_n ? (long long)nx : 0;
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+                xn[kk] = (AT)x[row + no + plane * k + i];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) s_row[w][kk][lane] = xv[kk + 1];
+        __syncthreads();
+        if (w > 0) {
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) xs[kk] = s_row[w - 1][kk][lane];
+        }
+        if (w < ST_TY - 1) {
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) xn[kk] = s_row[w + 1][kk][lane];
+        }
+    } else {
+        // binary32: every wave loads its south and north rows itself (the
+        // adjacent waves' rows, cache hits); no LDS exchange and no barrier,
+        // so no wave waits for the tile's slowest (measured faster in
+        // binary32; in FP64 the extra values in flight cost occupancy)
+        const long long so = has_s ? -(long long)nx : 0;
         const long long no = has_n ? (long long)nx : 0;
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+            xs[kk] = (AT)x[row + so + plane * k + i];
             xn[kk] = (AT)x[row + no + plane * k + i];
         }
-    }
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) s_row[w][kk][lane] = xv[kk + 1];
-    __syncthreads();
-    if (w > 0) {
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) xs[kk] = s_row[w - 1][kk][lane];
-    }
-    if (w < ST_TY - 1) {
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) xn[kk] = s_row[w + 1][kk][lane];
     }
     AT xw[KC], xe[KC];
 #pragma unroll
