@@ -25,13 +25,16 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 GRID = (512, 256, 64)
 K = 4
 TOL = 1e-8
+TIMED_STRIDE = 5   # timed region: dominant-kernel events on every 5th step (coprime with K)
 
 
-def alg_bytes(kernel, steps, k, n, s, xs=8):
-    """Algorithmic HBM bytes of one fault-free solve's launches of `kernel`.
-    Executed step t (1-based) has pass index nu = (t-1) mod k; the converging
-    step does not run the direction kernels.  Per launch (s = bytes per
-    stored value, xs = 8 for the FP64 iterate):
+def alg_bytes(kernel, steps, k, n, s, xs=8, stride=1):
+    """Algorithmic HBM bytes of one fault-free solve's launches of `kernel`
+    (of the steps whose number is a multiple of `stride`: the ones the timed
+    region times).  Executed step t (1-based) has pass index
+    nu = (t-1) mod k; the converging step does not run the direction
+    kernels.  Per launch (s = bytes per stored value, xs = 8 for the FP64
+    iterate):
       update_thomas  read r, L(p^nu); write r, e            4 s N
       stencil_dots   read e, L(p^0..nu)                     (nu + 2) s N
       dir_update     read e, r, p^0..nu, L(p^0..nu); write p^{nu+1},
@@ -40,6 +43,8 @@ def alg_bytes(kernel, steps, k, n, s, xs=8):
     """
     total = 0
     for t in range(1, steps + 1):
+        if t % stride:
+            continue
         nu = (t - 1) % k
         last = t == steps
         if kernel == "update_thomas":
@@ -118,10 +123,11 @@ def main():
     kernels = {q: {"launches": int(v[0]), "avg_us": (v[1] / v[0] * 1e3) if v[0] else 0.0} for q, v in kt_all.items()}
     dom = max(names, key=lambda q: kt_all[q][1])
 
-    # timed region: K whole solves; only the dominant kernel's launches carry
-    # HIP start/stop events (stamped by the dispatch, on the solve stream), so
-    # the timing costs the whole-solve rate as little as possible
-    s64.set_options(profile_kernels=2 << names.index(dom))
+    # timed region: K whole solves; only the dominant kernel's launches of
+    # every TIMED_STRIDE-th step carry HIP start/stop events (stamped by the
+    # dispatch, on the solve stream), so the timing costs the whole-solve rate
+    # as little as possible
+    s64.set_options(profile_kernels=(TIMED_STRIDE << 8) | (2 << names.index(dom)))
     s64.reset_kernel_times()
     torch.cuda.synchronize()
     steps_total, stats = 0, None
@@ -139,9 +145,11 @@ def main():
     print(f"[bench] fp64: {steps_per_solve} steps/solve, {wall / args.steps * 1e3:.2f} ms/solve, "
           f"true residual {stats['rel_res_true']:.3e}", flush=True)
 
-    # roofline of the dominant kernel, timed inside the timed region
+    # roofline of the dominant kernel, timed inside the timed region (the
+    # launches of every TIMED_STRIDE-th step, which for a stride coprime with
+    # k sample every pass index alike)
     launches, ms = kt[dom]
-    bytes_dom = alg_bytes(dom, steps_per_solve, K, n, 8) * args.steps
+    bytes_dom = alg_bytes(dom, steps_per_solve, K, n, 8, stride=TIMED_STRIDE) * args.steps
     achieved = bytes_dom / (ms * 1e-3) / 1e9
     step_bytes = sum(alg_bytes(q, steps_per_solve, K, n, 8) for q in names)
     whole_gbs = step_bytes * args.steps / wall / 1e9

@@ -89,10 +89,11 @@ typedef struct {
     int32_t levels_per_block;/* stencil kernels: levels per block (0 = auto)    */
     int32_t profile_kernels; /* time step kernels with a HIP event pair each,
                                 stamped by the kernel's own dispatch on the
-                                solve stream (ftgcr_kernel_times): 0 off,
-                                1 all three, else a mask of bit 1
+                                solve stream (ftgcr_kernel_times).  Bits 0-7:
+                                0 off, 1 all three, else a mask of bit 1
                                 update_thomas, bit 2 stencil_dots, bit 3
-                                dir_update                                      */
+                                dir_update; bits 8-15: a stride s > 1 times
+                                only steps whose number is a multiple of s   */
     int32_t batch_levels_per_block; /* ftgcr_solve_batch with this handle as
                                 the first member: stencil levels per block of
                                 the combined launches (1, 2, 4, 8 or 16; 0 =

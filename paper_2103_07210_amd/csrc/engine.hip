@@ -361,11 +361,15 @@ struct Runner {
     template <class F>
     void timed(int cls, F&& launch)
     {
-        // profile_kernels: 1 times all three step kernels; any other nonzero
-        // value is a mask (bit 1 update_thomas, bit 2 stencil_dots, bit 3
-        // dir_update)
-        const int mask = h->opt.profile_kernels == 1 ? 0xE : h->opt.profile_kernels;
-        if (!(mask & (2 << cls))) {
+        // profile_kernels, bits 0-7: 1 times all three step kernels, any
+        // other nonzero value is a mask (bit 1 update_thomas, bit 2
+        // stencil_dots, bit 3 dir_update); bits 8-15: a stride s > 1 times
+        // only the steps whose number is a multiple of s (for s coprime with
+        // k the sample covers every pass index alike)
+        const int sel = h->opt.profile_kernels & 0xFF;
+        const int stride = (h->opt.profile_kernels >> 8) & 0xFF;
+        const int mask = sel == 1 ? 0xE : sel;
+        if (!(mask & (2 << cls)) || (stride > 1 && cur_step % stride != 0)) {
             launch(nullptr, nullptr);
             return;
         }

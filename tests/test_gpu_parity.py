@@ -508,3 +508,32 @@ def test_mixed_preconditioner_matches_fp64_step_counts(ft, shape):
     assert st64["status"] == stm["status"] == ft.CONVERGED
     assert stm["rel_res_true"] <= 1.001e-8
     assert stm["steps_executed"] <= 1.10 * st64["steps_executed"] + 8, (stm["steps_executed"], st64["steps_executed"])
+
+
+def test_kernel_times_and_sampled_timing(ft):
+    """profile_kernels: timing every step kernel counts one launch per
+    executed step; a mask with a step stride times only the chosen kernel on
+    every stride-th step; timing changes no result."""
+    _say("kernel timing")
+    pb = Problem(64, 32, 8, hill_amp=0.6)
+    rhs = I.rhs(pb, 5)
+    s = ft.Solver(pb, kmax=4)
+    x0, st0 = s.solve(rhs, tol=1e-10, k=4)
+    steps = st0["steps_executed"]
+    s.set_options(profile_kernels=1)
+    s.reset_kernel_times()
+    x1, st1 = s.solve(rhs, tol=1e-10, k=4)
+    kt = s.kernel_times()
+    assert kt["update_thomas"][0] == steps
+    assert kt["stencil_dots"][0] in (steps - 1, steps) and kt["dir_update"][0] in (steps - 1, steps)
+    assert all(v[1] > 0 for v in kt.values())
+    s.set_options(profile_kernels=(5 << 8) | (2 << 2))
+    s.reset_kernel_times()
+    x2, st2 = s.solve(rhs, tol=1e-10, k=4)
+    kt2 = s.kernel_times()
+    assert kt2["update_thomas"][0] == 0 and kt2["stencil_dots"][0] == 0
+    assert kt2["dir_update"][0] in (steps // 5 - 1, steps // 5) and kt2["dir_update"][1] > 0
+    s.close()
+    for x, st in ((x1, st1), (x2, st2)):
+        assert st["steps_executed"] == steps
+        assert np.array_equal(x.cpu().numpy(), x0.cpu().numpy())
