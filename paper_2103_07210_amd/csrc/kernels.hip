@@ -1404,11 +1404,16 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
     double a[KC], p[KC], xa[KC], r[KC];
     // p starts from e: the stencil's own centre values (no second load)
     stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a, p);
+    // r is needed only for the next beta's products at the end: binary32
+    // loads it there (the registers it frees give that kernel a sixth wave
+    // per SIMD); FP64 loads it with the iterate (there a late load is
+    // slower, the occupancy being the same)
+    constexpr bool R_LATE = sizeof(T) == 4;
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
         const long long c = c0 + plane * kq;
-        r[kk] = (double)rv[c];
+        if constexpr (!R_LATE) r[kk] = (double)rv[c];
         xa[kk] = xupd ? __builtin_nontemporal_load(&xb[c]) : 0.0;
     }
     // sums over l in ascending order; term l + 1's loads are issued before
@@ -1451,6 +1456,13 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
                 a[kk] = fma(al, (double)ab[l % PD][kk], a[kk]);
                 if (xupd) xa[kk] = fma(bl, (double)pb[l % PD][kk], xa[kk]);
             }
+        }
+    }
+    if constexpr (R_LATE) {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+            r[kk] = (double)rv[c0 + plane * kq];
         }
     }
     double acc_num = 0.0, acc_d = 0.0;
