@@ -28,32 +28,85 @@ TOL = 1e-8
 TIMED_STRIDE = 5   # timed region: dominant-kernel events on every 5th step (coprime with K)
 
 
-def alg_bytes(kernel, steps, k, n, s, xs=8, stride=1):
-    """Algorithmic HBM bytes of one fault-free solve's launches of `kernel`
-    (of the steps whose number is a multiple of `stride`: the ones the timed
-    region times).  Executed step t (1-based) has pass index
-    nu = (t-1) mod k; the converging step does not run the direction
-    kernels.  Per launch (s = bytes per stored value, xs = 8 for the FP64
-    iterate):
-      update_thomas  read r, L(p^nu); write r, e            4 s N
-      stencil_dots   read e, L(p^0..nu)                     (nu + 2) s N
-      dir_update     read e, r, p^0..nu, L(p^0..nu); write p^{nu+1},
-                     L(p^{nu+1})                            (2 nu + 6) s N
-                     + at nu = k-1 read and write x         + 2 xs N
-    """
+# Algorithmic bytes: the method's own HBM traffic when every operand is read
+# once per phase between two global reductions and e, L(e) are recomputed
+# rather than stored (s = bytes per stored value, N cells):
+#   update phase U(nu): read r, L(p^nu), x, p^nu, L(p^0..nu-1); write r, x
+#                       (nu + 6) s N
+#   direction phase O(nu): read r, p^0..nu, L(p^0..nu); write p^{nu+1},
+#                       L(p^{nu+1})                            (2 nu + 5) s N
+#   backup: [x, r, p^0, L(p^0)] written once per cycle          4 s N
+# so a step moves W(nu) = (3 nu + 11) s N plus 4 s N per cycle (16.5 sweeps
+# per step at k = 4).  The converging step runs U only.  Once per solve (or
+# refinement round) the initial residual, P^{-1} r0 and A p0 move 6 s N, and
+# every FP64 true-residual pass (x, R read, r_t written) 3 * 8 N.
+# The design's own kernels move more: the column pass stores e (4 s N: r,
+# L(p^nu) read, r+, e written), the dots pass re-reads it ((nu + 2) s N), the
+# direction pass re-reads it with r ((2 nu + 6) s N) and the iterate is read
+# and written once per cycle (2 * 8 N at nu = k - 1); that excess is reported
+# as design overhead, not as work.
+
+
+def pass_bytes(kernel, nu, k, n, s, xs=8, design=False):
+    """Bytes of one launch of a step kernel at pass index nu: the method's
+    algorithmic bytes of the phase it implements (dir_update: the direction
+    phase plus the once-per-cycle iterate update it carries), or with
+    design=True what the kernel moves by design."""
+    x_upd = 2 * xs * n if nu == k - 1 else 0
+    if kernel == "dir_update":
+        return ((2 * nu + 6) if design else (2 * nu + 5)) * s * n + x_upd
+    if kernel == "update_thomas":
+        return 4 * s * n
+    if kernel == "stencil_dots":
+        return (nu + 2) * s * n
+    raise KeyError(kernel)
+
+
+def alg_bytes(kernel, steps, k, n, s, xs=8, stride=1, design=False):
+    """Bytes of one fault-free solve's launches of `kernel` (of the steps
+    whose number is a multiple of `stride`: the ones the timed region times).
+    Executed step t (1-based) has pass index nu = (t-1) mod k; the
+    converging step does not run the direction kernels."""
     total = 0
     for t in range(1, steps + 1):
         if t % stride:
             continue
         nu = (t - 1) % k
-        last = t == steps
-        if kernel == "update_thomas":
-            total += 4 * s * n
-        elif kernel == "stencil_dots" and not last:
-            total += (nu + 2) * s * n
-        elif kernel == "dir_update" and not last:
-            total += (2 * nu + 6) * s * n + (2 * xs * n if nu == k - 1 else 0)
+        if kernel != "update_thomas" and t == steps:
+            continue
+        total += pass_bytes(kernel, nu, k, n, s, xs, design)
     return total
+
+
+def solve_bytes(steps, k, n, s, rounds=1, residual_passes=1, design=False):
+    """Bytes of a whole fault-free solve of `steps` executed steps in
+    `rounds` refinement rounds (FP64: one round) with `residual_passes` FP64
+    true-residual passes.  The pass index runs over the executed steps as
+    one sequence (a round boundary shifts it by less than k steps: under
+    0.5% of a solve).  design=True: what the design's kernels move."""
+    total = 0
+    for t in range(1, steps + 1):
+        nu = (t - 1) % k
+        last = t == steps
+        if design:
+            total += sum(pass_bytes(q, nu, k, n, s, design=True) for q in
+                         (("update_thomas",) if last else ("update_thomas", "stencil_dots", "dir_update")))
+        else:
+            total += (nu + 6) * s * n + (0 if last else (2 * nu + 5) * s * n)
+    if not design:
+        total += 4 * s * n * ((steps + k - 1) // k)
+    total += 6 * s * n * rounds + 3 * 8 * n * residual_passes
+    return total
+
+
+def step_frac(steps, k, n, s, ms, rounds=1, residual_passes=1):
+    """Whole-solve rate on the algorithmic bytes against the HBM peak, and
+    the design's bytes over them."""
+    alg = solve_bytes(steps, k, n, s, rounds, residual_passes)
+    des = solve_bytes(steps, k, n, s, rounds, residual_passes, design=True)
+    gbs = alg / (ms * 1e-3) / 1e9
+    return {"ms": ms, "steps": steps, "alg_bytes": alg, "alg_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "design_bytes": des, "design_overhead": des / alg - 1.0}
 
 
 def cpu_baseline(pb, rhs, steps=24):
@@ -79,7 +132,12 @@ def main():
                     help="short run for counter passes: one FP64 solve and the 1 GiB copy probe only")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member batched ensemble timing")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024x512x96 solves")
+    ap.add_argument("--grid", default="512,256,64",
+                    help="with --profile-run: the grid of the profiled FP64 solve (nlon,nlat,nz)")
     args = ap.parse_args()
+    grid = tuple(int(v) for v in args.grid.split(","))
+    if grid != GRID and not args.profile_run:
+        ap.error("--grid is for --profile-run only; the benchmark workload is 512x256x64")
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu, args.mixed_steps, args.no_ensemble, args.no_large = 1, 0, True, 0, True, True
     if args.gpus != 1:
@@ -94,12 +152,13 @@ def main():
     from paper_2103_07210_amd import inputs as I
 
     torch.cuda.set_device(0)
-    pb = I.Problem(*GRID)
+    pb = I.Problem(*grid)
     n = pb.n
-    rhs_np = I.rhs(pb, I.SEEDS["c3_rhs"])
+    grid_tag = "x".join(str(v) for v in grid)
+    rhs_np = I.rhs(pb, I.SEEDS["c3_rhs" if grid == GRID else "c5_rhs"])
     rhs = torch.from_numpy(rhs_np).cuda()
     x = torch.zeros_like(rhs)
-    print(f"[bench] grid {GRID} N={n} k={K} tol={TOL}", flush=True)
+    print(f"[bench] grid {grid} N={n} k={K} tol={TOL}", flush=True)
 
     s64 = ftgcr.Solver(pb, "fp64", kmax=K, poll_steps=32)
     kc64 = s64.autotune(rhs, k=K, steps=24) if not args.profile_run else s64.options()["levels_per_block"]
@@ -150,25 +209,21 @@ def main():
     # k sample every pass index alike)
     launches, ms = kt[dom]
     bytes_dom = alg_bytes(dom, steps_per_solve, K, n, 8, stride=TIMED_STRIDE) * args.steps
+    design_dom = alg_bytes(dom, steps_per_solve, K, n, 8, stride=TIMED_STRIDE, design=True) * args.steps
     achieved = bytes_dom / (ms * 1e-3) / 1e9
-    step_bytes = sum(alg_bytes(q, steps_per_solve, K, n, 8) for q in names)
-    whole_gbs = step_bytes * args.steps / wall / 1e9
+    whole_gbs = solve_bytes(steps_per_solve, K, n, 8) * args.steps / wall / 1e9
+    for q in names:
+        v = kernels[q]
+        if v["launches"]:
+            b = alg_bytes(q, steps_per_solve, K, n, 8, design=True) / v["launches"]
+            v["design_bytes_per_launch"] = b
+            v["design_gbs"] = b / (v["avg_us"] * 1e-6) / 1e9
     from paper_2103_07210_amd.profsum import read_traffic
-    traffic = read_traffic(os.path.join(ROOT, "profiles", "traffic_dir_update_fp64_512x256x64.md"))
+    traffic = read_traffic(os.path.join(ROOT, "profiles", f"traffic_dir_update_fp64_{grid_tag}.md"))
 
-    # device copy probe: 1 GiB read + 1 GiB written by the runtime's copy kernel
-    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * (1 << 30) / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
-    del src, dst
+    # HBM copy probe: the library's streaming copy kernel, 1 GiB read and
+    # 1 GiB written per copy
+    copy_gbs = ftgcr.bw_probe(1 << 30, reps=5)
 
     # mixed precision, same problem, time to the same 1e-8 true residual,
     # against FP64 solves timed the same way (no per-kernel events)
@@ -202,6 +257,7 @@ def main():
                        "steps_on": steps_per_solve, "steps_off": st_off["steps_executed"]}
         print(f"[bench] FT on {fp64_ms:.2f} ms, FT off {off_ms:.2f} ms", flush=True)
         s_off.close()
+    fracs = {f"{grid_tag}_fp64": step_frac(steps_per_solve, K, n, 8, fp64_ms)}
     mixed = None
     if args.mixed_steps > 0:
         sm = ftgcr.Solver(pb, "mixed", kmax=K, poll_steps=32)
@@ -226,6 +282,9 @@ def main():
                  "fp64_true_residual": stats["rel_res_true"], "mixed_true_residual": mstats["rel_res_true"],
                  "mixed_inner_steps": mstats["steps_executed"], "mixed_refinements": mstats["refinements"],
                  "mixed_vs_fp64_solution_rel_diff": mixed_err, "mixed_levels_per_block": kcm}
+        fracs["512x256x64_mixed"] = step_frac(mstats["steps_executed"], K, n, 4, mixed_med,
+                                              rounds=mstats["refinements"],
+                                              residual_passes=mstats["refinements"] + 1)
 
     # 64-member ensemble (sizes 64x32x8 .. 256x128x32, 6 members with a
     # fault): one batched launch sequence against the members one by one
@@ -250,10 +309,15 @@ def main():
         seq_ms = (time.perf_counter() - t1) * 1e3
         steps_all = sum(b["steps_executed"] for b in bst)
         points = sum(mb.problem.n for mb in members)
+        # aggregate algorithmic bytes of the members' solves (rolled-back
+        # steps of the faulty members counted as executed) over the batched time
+        ens_bytes = sum(solve_bytes(b["steps_executed"], 3, mb.problem.n, 8) for b, mb in zip(bst, members))
         ensemble = {"members": 64, "points": points, "k": 3, "tol": 1e-10, "levels_per_block": batch_kc,
                     "batched_ms": batched_ms, "sequential_ms": seq_ms,
                     "member_steps_total": steps_all, "member_steps_per_s_batched": steps_all / batched_ms * 1e3,
                     "all_converged": all(b["status"] == 0 for b in bst),
+                    "alg_bytes": ens_bytes, "alg_gbs": ens_bytes / (batched_ms * 1e-3) / 1e9,
+                    "frac": ens_bytes / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                     "detections": sum(b["detections"] for b in bst)}
         print(f"[bench] ensemble: batched {batched_ms:.1f} ms, one by one {seq_ms:.1f} ms", flush=True)
         for sv in solvers:
@@ -302,16 +366,23 @@ def main():
             x_l.zero_()
             sl.solve(rhs_l, x_l, tol=TOL, k=K)
             rec = {"levels_per_block": kcl}
-            for name, pln in (("clean", []), ("fault", plan)):
-                x_l.zero_()
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                _, stl = sl.solve(rhs_l, x_l, tol=TOL, k=K, plan=pln)
-                torch.cuda.synchronize()
-                rec[name] = {"ms": (time.perf_counter() - t1) * 1e3, "steps_executed": stl["steps_executed"],
+            for name, pln, reps in (("clean", [], 3), ("fault", plan, 1)):
+                runs = []
+                for _ in range(reps):
+                    x_l.zero_()
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    _, stl = sl.solve(rhs_l, x_l, tol=TOL, k=K, plan=pln)
+                    torch.cuda.synchronize()
+                    runs.append((time.perf_counter() - t1) * 1e3)
+                rec[name] = {"ms": float(np.median(runs)), "steps_executed": stl["steps_executed"],
                              "steps_wasted": stl["steps_wasted"], "detections": stl["detections"],
                              "refinements": stl["refinements"], "rel_res_true": stl["rel_res_true"]}
             large[prec] = rec
+            cl = rec["clean"]
+            fracs[f"{pl.nx}x{pl.ny}x{pl.nz}_{prec}"] = step_frac(
+                cl["steps_executed"], K, pl.n, 8 if prec == "fp64" else 4, cl["ms"],
+                rounds=max(1, cl["refinements"]), residual_passes=cl["refinements"] + 1)
             print(f"[bench] {pl.nx}x{pl.ny}x{pl.nz} {prec}: clean {rec['clean']['ms']:.1f} ms "
                   f"({rec['clean']['steps_executed']} steps), 10% r block fault {rec['fault']['ms']:.1f} ms "
                   f"({rec['fault']['detections']} detections, {rec['fault']['steps_wasted']} wasted)", flush=True)
@@ -341,6 +412,7 @@ def main():
                    "grid": list(GRID), "k": K, "tol": TOL, "steps_per_solve": steps_per_solve,
                    "levels_per_block": kc64},
         "hbm_gbs_algorithmic": whole_gbs,
+        "step_frac": fracs,
         "time_to_1e-8_ms": mixed,
         "ft_overhead_fault_free": ft_overhead,
         "kernels": kernels,
@@ -352,6 +424,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic if dom == "dir_update" else None,
                      "avg_launch_us": ms / launches * 1e3 if launches else None,
                      "alg_bytes_per_launch": bytes_dom / (launches or 1),
+                     "design_bytes_per_launch": design_dom / (launches or 1),
                      "frac_of_copy_probe": achieved / copy_gbs},
         "cpu_baseline": cpu,
     }

@@ -255,6 +255,16 @@ ftgcr_status ftgcr_reset_kernel_times(ftgcr_handle* h);
 
 void ftgcr_destroy(ftgcr_handle* h);
 
+/* HBM bandwidth probe (measurement, no solver state): copies `bytes` from
+ * src_dev to dst_dev once to warm up, then `reps` times with a plain
+ * streaming copy kernel on hip_stream (NULL: default stream), and writes the
+ * achieved rate 2 * bytes * reps / elapsed (read plus write, GB/s = 1e9 B/s)
+ * to *gbs.  The two buffers are device memory of the current device, 16-byte
+ * aligned, not overlapping; bytes is a positive multiple of 16.  Synchronous.
+ * Errors are reported by ftgcr_last_error(NULL). */
+ftgcr_status ftgcr_bw_probe(const void* src_dev, void* dst_dev, size_t bytes, int32_t reps, void* hip_stream,
+                            double* gbs);
+
 /* Message of the last failed call on h (or of the last failed create when h
  * is NULL).  Valid until the next call on the same handle. */
 const char* ftgcr_last_error(const ftgcr_handle* h);

@@ -85,6 +85,20 @@ struct ftgcr_handle {
     std::vector<Pending> pending;
     double kt_ms[3] = {0, 0, 0};
     long long kt_n[3] = {0, 0, 0};
+
+    // batched solves led by this handle: device tables kept between calls
+    // (grown, never per call) and the captured step chunk of the last
+    // launch table shape
+    struct Batch {
+        int cap = 0;
+        Inst<double>* inst = nullptr;   // launch table (running members)
+        int* blk0 = nullptr;            // its col, st and dir prefixes (cap+1 each)
+        long long* status = nullptr;    // 2 per member
+        Inst<double>* all = nullptr;    // every member, in order
+        int* blk0_all = nullptr;
+        hipGraphExec_t graph = nullptr;
+        long long graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    } batch;
 };
 
 namespace {
@@ -193,13 +207,13 @@ Layout layout(const ftgcr_handle* h)
 }
 
 template <typename T>
-Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x)
+Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x, void* ws)
 {
     Inst<T> in;
     std::memset(&in, 0, sizeof in);
     in.g = h->geo;
     const Layout L = layout(h);
-    char* p = (char*)h->ws;
+    char* p = (char*)ws;
     for (int l = 0; l <= h->kmax; ++l) { in.P[l] = (T*)p; p += L.vec; }
     for (int l = 0; l <= h->kmax; ++l) { in.AP[l] = (T*)p; p += L.vec; }
     for (int q = 0; q < 3; ++q) { in.R[q] = (T*)p; p += L.vec; }
@@ -355,6 +369,9 @@ struct Runner {
     ftgcr_handle* h;
     Table<T> tb;
     hipStream_t s;
+    // no allocation of any kind: no graph capture or instantiation, no
+    // timing events (kernel timing and graph replay are skipped)
+    bool noalloc = false;
 
     long long cur_step = 0;
 
@@ -366,7 +383,7 @@ struct Runner {
         // stencil_dots, bit 3 dir_update); bits 8-15: a stride s > 1 times
         // only the steps whose number is a multiple of s (for s coprime with
         // k the sample covers every pass index alike)
-        const int sel = h->opt.profile_kernels & 0xFF;
+        const int sel = noalloc ? 0 : (h->opt.profile_kernels & 0xFF);
         const int stride = (h->opt.profile_kernels >> 8) & 0xFF;
         const int mask = sel == 1 ? 0xE : sel;
         if (!(mask & (2 << cls)) || (stride > 1 && cur_step % stride != 0)) {
@@ -505,7 +522,7 @@ struct Runner {
                 long long cnt = want;
                 if (evp < evs.size()) cnt = std::min<long long>(cnt, evs[evp].step - 1 - launched);
                 cnt = std::max<long long>(cnt, 1);
-                if (cnt == chunk && h->opt.use_graphs && !h->opt.profile_kernels) {
+                if (cnt == chunk && h->opt.use_graphs && !h->opt.profile_kernels && !noalloc) {
                     ftgcr_status rc = replay(chunk);
                     if (rc != FTGCR_OK) return rc;
                 } else {
@@ -535,7 +552,11 @@ struct Runner {
     }
 };
 
-ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::vector<DevEvent>& out)
+// Copy a fault plan's entry lists to the device.  staging == nullptr: into
+// the handle's staging buffers (grown with hipMalloc when too small); else
+// into `staging` (staging_bytes of device memory), with no allocation.
+ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::vector<DevEvent>& out,
+                          void* staging = nullptr, size_t staging_bytes = 0)
 {
     out.clear();
     if (!plan || plan->n_events <= 0) return FTGCR_OK;
@@ -556,7 +577,14 @@ ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::ve
         }
         if (e.idx || e.bits) need += (size_t)e.count;
     }
-    if (need > h->ev_cap) {
+    long long* ev_idx = h->ev_idx;
+    unsigned char* ev_bits = h->ev_bits;
+    if (staging) {
+        if (need * (sizeof(long long) + 1) > staging_bytes)
+            return fail(h, FTGCR_E_WORKSPACE, "fault plan entries exceed the scratch memory left by the workspace");
+        ev_idx = (long long*)staging;
+        ev_bits = (unsigned char*)(ev_idx + need);
+    } else if (need > h->ev_cap) {
         if (h->ev_idx) (void)hipFree(h->ev_idx);
         if (h->ev_bits) (void)hipFree(h->ev_bits);
         h->ev_idx = nullptr;
@@ -565,6 +593,8 @@ ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::ve
         HIP_TRY(h, hipMalloc(&h->ev_idx, need * sizeof(long long)));
         HIP_TRY(h, hipMalloc(&h->ev_bits, need));
         h->ev_cap = need;
+        ev_idx = h->ev_idx;
+        ev_bits = h->ev_bits;
     }
     size_t off = 0;
     for (int q = 0; q < plan->n_events; ++q) {
@@ -578,12 +608,12 @@ ftgcr_status stage_events(ftgcr_handle* h, const ftgcr_fault_plan* plan, std::ve
         d.idx = nullptr;
         d.bits = nullptr;
         if (e.idx && e.count > 0) {
-            HIP_TRY(h, hipMemcpy(h->ev_idx + off, e.idx, (size_t)e.count * sizeof(long long), hipMemcpyHostToDevice));
-            d.idx = h->ev_idx + off;
+            HIP_TRY(h, hipMemcpy(ev_idx + off, e.idx, (size_t)e.count * sizeof(long long), hipMemcpyHostToDevice));
+            d.idx = ev_idx + off;
         }
         if (e.bits && e.count > 0) {
-            HIP_TRY(h, hipMemcpy(h->ev_bits + off, e.bits, (size_t)e.count, hipMemcpyHostToDevice));
-            d.bits = h->ev_bits + off;
+            HIP_TRY(h, hipMemcpy(ev_bits + off, e.bits, (size_t)e.count, hipMemcpyHostToDevice));
+            d.bits = ev_bits + off;
         }
         if (e.idx || e.bits) off += (size_t)e.count;
         if (e.count > 0 && e.step >= 1) out.push_back(d);
@@ -625,21 +655,26 @@ void fill_stats(ftgcr_handle* h, const SolveState& st, int refinements, float ms
     (void)h;
 }
 
+// One solve with the working vectors in `ws` (layout(h).total bytes).
+// staging != nullptr: the fault plan's entry lists go there and nothing is
+// allocated (no graphs, no timing events): the allocation-free entry point.
 template <typename T>
 ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double tol, int k,
-                        const ftgcr_fault_plan* plan, ftgcr_stats* stats)
+                        const ftgcr_fault_plan* plan, ftgcr_stats* stats, void* ws,
+                        void* staging = nullptr, size_t staging_bytes = 0)
 {
     using L = Launch<T>;
     hipStream_t s = h->stream;
     std::vector<DevEvent> evs;
-    ftgcr_status rc = stage_events(h, plan, evs);
+    ftgcr_status rc = stage_events(h, plan, evs, staging, staging_bytes);
     if (rc != FTGCR_OK) return rc;
 
-    Inst<T> in = make_inst<T>(h, rhs, x);
+    Inst<T> in = make_inst<T>(h, rhs, x, ws);
     h->nt_ap = nt_ap_hint(k, h->geo.n, (int)sizeof(T));
     HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1}, s};
+    run.noalloc = staging != nullptr;
     const Table<T>& tb = run.tb;
     const bool mixed = h->precision == FTGCR_MIXED;
     const long long max_steps = h->opt.max_steps;
@@ -720,15 +755,44 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
 // Thomas depth and one stencil tiling.  Finished members are dropped from the
 // launch table at the next status read.
 
-struct BatchTables {
-    Inst<double>* inst = nullptr;   // device
-    int* blk0 = nullptr;            // device: col, st and dir prefixes (n+1 each)
-    long long* status = nullptr;    // device: 2 per member
-    int cols = 0, sts = 0, dirs = 0;
+// Device tables of a batch of n members on the leading handle, grown when n
+// exceeds what earlier calls needed (the only allocation of a batched solve).
+ftgcr_status batch_tables(ftgcr_handle* h0, int n)
+{
+    auto& B = h0->batch;
+    if (n <= B.cap) return FTGCR_OK;
+    if (B.graph) (void)hipGraphExecDestroy(B.graph);
+    (void)hipFree(B.inst);
+    (void)hipFree(B.blk0);
+    (void)hipFree(B.status);
+    (void)hipFree(B.all);
+    (void)hipFree(B.blk0_all);
+    B = ftgcr_handle::Batch{};
+    const size_t pre = 3 * (size_t)(n + 1) * sizeof(int);
+    if (hipMalloc(&B.inst, n * sizeof(Inst<double>)) != hipSuccess || hipMalloc(&B.blk0, pre) != hipSuccess ||
+        hipMalloc(&B.status, 2 * n * sizeof(long long)) != hipSuccess ||
+        hipMalloc(&B.all, n * sizeof(Inst<double>)) != hipSuccess || hipMalloc(&B.blk0_all, pre) != hipSuccess) {
+        (void)hipFree(B.inst);
+        (void)hipFree(B.blk0);
+        (void)hipFree(B.status);
+        (void)hipFree(B.all);
+        (void)hipFree(B.blk0_all);
+        B = ftgcr_handle::Batch{};
+        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
+    }
+    B.cap = n;
+    return FTGCR_OK;
+}
+
+// Launch-table shape of the running members: blocks of the three grids.
+struct BatchShape {
+    int n = 0, cols = 0, sts = 0, dirs = 0;
 };
 
+// Upload the members' instance records and block prefixes into `inst` /
+// `blk0` (device, capacity for members.size()).
 ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins, const std::vector<int>& members,
-                          BatchTables& bt, Table<double>& tb)
+                          Inst<double>* inst, int* blk0, BatchShape& sh, Table<double>& tb)
 {
     const int na = (int)members.size();
     std::vector<Inst<double>> act(na);
@@ -739,15 +803,48 @@ ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins
         pre[na + 1 + q + 1] = pre[na + 1 + q] + act[q].nblk_st;
         pre[2 * (na + 1) + q + 1] = pre[2 * (na + 1) + q] + act[q].nblk_dir;
     }
-    HIP_TRY(h0, hipMemcpy(bt.inst, act.data(), na * sizeof(Inst<double>), hipMemcpyHostToDevice));
-    HIP_TRY(h0, hipMemcpy(bt.blk0, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
-    bt.cols = pre[na];
-    bt.sts = pre[2 * na + 1];
-    bt.dirs = pre[3 * na + 2];
-    tb = Table<double>{bt.inst, bt.blk0, bt.blk0 + na + 1, bt.blk0 + 2 * (na + 1), na};
+    HIP_TRY(h0, hipMemcpy(inst, act.data(), na * sizeof(Inst<double>), hipMemcpyHostToDevice));
+    HIP_TRY(h0, hipMemcpy(blk0, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
+    sh.n = na;
+    sh.cols = pre[na];
+    sh.sts = pre[2 * na + 1];
+    sh.dirs = pre[3 * na + 2];
+    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na};
     return FTGCR_OK;
 }
 
+// One batched step over the launch table; `mid` are the step's e events
+// (member, event), injected by `apply` between the decision and the dots
+// pass.
+template <class Apply>
+void batch_step(const Table<double>& tb, const BatchShape& sh, int H, int kc, bool nt_ap, hipStream_t s,
+                const std::vector<std::pair<int, const DevEvent*>>& mid, Apply&& apply)
+{
+    using L = Launch<double>;
+    L::update_thomas(tb, sh.cols, H, 0, s);
+    if (!mid.empty()) {
+        L::finish_col(tb, 0, s);
+        for (const auto& me : mid) apply(me.first, *me.second);
+        L::stencil_dots(tb, sh.sts, kc, 0, s);
+        L::finish_alpha(tb, s);
+    } else {
+        L::stencil_dots(tb, sh.sts, kc, 1, s);
+        L::finish_step(tb, s);
+    }
+    L::dir_update(tb, sh.dirs, kc < 4 ? kc : 4, 0, nt_ap, s);
+    L::finish_beta(tb, 0, s);
+}
+
+// Members step together: each launch of a step kernel covers the blocks of
+// every member of the launch table (block -> member by a prefix search),
+// and the one-block reductions run one block per member.  All members share
+// one Thomas depth and one stencil tiling.  Steps without fault events are
+// replayed from a captured graph of `poll_steps` steps (options.use_graphs
+// of the leading handle), captured again only when the launch table changes
+// shape.  A member that finishes does no work in later launches (every step
+// kernel returns at once for a solve that is no longer running); finished
+// members are compacted out of the table at a status read once their blocks
+// are an eighth of the table's or more.
 ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* const* rhs, double* const* x,
                               const double* tol, int k, const ftgcr_fault_plan* plans, ftgcr_stats* stats)
 {
@@ -772,7 +869,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     std::vector<std::vector<DevEvent>> evs(n);
     for (int m = 0; m < n; ++m) {
         ftgcr_handle* h = hs[m];
-        ins[m] = make_inst<double>(h, rhs[m], x[m]);
+        ins[m] = make_inst<double>(h, rhs[m], x[m], h->ws);
         ins[m].kc = kc;
         ins[m].tz = (h->geo.nz + kc - 1) / kc;
         ins[m].nblk_st = ins[m].tx * ins[m].ty * ins[m].tz;
@@ -783,75 +880,35 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
             return rc;
         }
     }
-    BatchTables bt;
-    auto cleanup = [&]() {
-        if (bt.inst) (void)hipFree(bt.inst);
-        if (bt.blk0) (void)hipFree(bt.blk0);
-        if (bt.status) (void)hipFree(bt.status);
-    };
-    if (hipMalloc(&bt.inst, n * sizeof(Inst<double>)) != hipSuccess ||
-        hipMalloc(&bt.blk0, 3 * (n + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&bt.status, 2 * n * sizeof(long long)) != hipSuccess) {
-        cleanup();
-        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
-    }
-    // full table (members in order) and the per-member single tables used by
-    // the fault-event kernels
-    Inst<double>* all = nullptr;
-    if (hipMalloc(&all, n * sizeof(Inst<double>)) != hipSuccess) {
-        cleanup();
-        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
-    }
-    auto cleanup_all = [&]() {
-        cleanup();
-        (void)hipFree(all);
-    };
-    if (hipMemcpy(all, ins.data(), n * sizeof(Inst<double>), hipMemcpyHostToDevice) != hipSuccess) {
-        cleanup_all();
-        return fail(h0, FTGCR_E_HIP, "batch table upload failed");
-    }
+    ftgcr_status rc = batch_tables(h0, n);
+    if (rc != FTGCR_OK) return rc;
+    auto& B = h0->batch;
     std::vector<int> members(n);
     for (int m = 0; m < n; ++m) members[m] = m;
-    // the full table keeps its own prefix arrays (the launch table is
-    // compacted in place as members finish)
-    int* blk0_all = nullptr;
-    std::vector<int> pre_all(3 * (n + 1), 0);
-    for (int m = 0; m < n; ++m) {
-        pre_all[m + 1] = pre_all[m] + ins[m].nblk_col;
-        pre_all[n + 1 + m + 1] = pre_all[n + 1 + m] + ins[m].nblk_st;
-        pre_all[2 * (n + 1) + m + 1] = pre_all[2 * (n + 1) + m] + ins[m].nblk_dir;
-    }
-    if (hipMalloc(&blk0_all, pre_all.size() * sizeof(int)) != hipSuccess ||
-        hipMemcpy(blk0_all, pre_all.data(), pre_all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-        if (blk0_all) (void)hipFree(blk0_all);
-        cleanup_all();
-        return fail(h0, FTGCR_E_NOMEM, "batch table allocation failed");
-    }
-    auto cleanup_full = [&]() {
-        cleanup_all();
-        (void)hipFree(blk0_all);
-    };
-    const Table<double> tb_all{all, blk0_all, blk0_all + n + 1, blk0_all + 2 * (n + 1), n};
-    const int sts_all = pre_all[2 * n + 1];
+    // the full table (every member, in order) for the passes before and
+    // after the steps, and the per-member single tables of the fault-event
+    // kernels
+    BatchShape sh_all;
+    Table<double> tb_all{};
+    rc = upload_batch(h0, ins, members, B.all, B.blk0_all, sh_all, tb_all);
+    if (rc != FTGCR_OK) return rc;
+    BatchShape sh;
     Table<double> tb{};
-    ftgcr_status rc = upload_batch(h0, ins, members, bt, tb);
-    if (rc != FTGCR_OK) {
-        cleanup_full();
-        return rc;
-    }
-    auto single = [&](int m) { return Table<double>{all + m, hs[m]->blk0, hs[m]->blk0 + 2, hs[m]->blk0 + 4, 1}; };
+    rc = upload_batch(h0, ins, members, B.inst, B.blk0, sh, tb);
+    if (rc != FTGCR_OK) return rc;
+    auto single = [&](int m) { return Table<double>{B.all + m, hs[m]->blk0, hs[m]->blk0 + 2, hs[m]->blk0 + 4, 1}; };
 
     hipEvent_t e0 = h0->ev_start, e1 = h0->ev_stop;
     (void)hipEventRecord(e0, s);
     for (int m = 0; m < n; ++m)
         L::init_state(single(m), k, hs[m]->opt.ft, 0, hs[m]->opt.max_steps, tol[m] * tol[m], 1, 1, s);
-    L::residual(tb, bt.sts, kc, 1, 1, s);
-    L::update_thomas(tb, bt.cols, H, 1, s);
+    L::residual(tb, sh.sts, kc, 1, 1, s);
+    L::update_thomas(tb, sh.cols, H, 1, s);
     L::finish_col(tb, 1, s);
     long long n_total = 0;
     for (int m = 0; m < n; ++m) n_total += hs[m]->geo.n;
     const bool nt_ap = nt_ap_hint(k, n_total, (int)sizeof(double));
-    L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 1, nt_ap, s);
+    L::dir_update(tb, sh.dirs, kc < 4 ? kc : 4, 1, nt_ap, s);
     L::finish_beta(tb, 1, s);
 
     const int chunk = std::max(1, h0->opt.poll_steps);
@@ -859,19 +916,44 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     for (int m = 0; m < n; ++m) max_cap = std::max<long long>(max_cap, hs[m]->opt.max_steps);
     std::vector<size_t> evp(n, 0);
     std::vector<long long> host_status(2 * n);
+    auto apply = [&](int m, const DevEvent& ev) {
+        const Table<double> t1 = single(m);
+        const long long nn = hs[m]->geo.n;
+        L::event_prep(t1, ev.vec, s);
+        if (ev.vec != FTGCR_V_E) L::event_copy(t1, (int)std::min<long long>((nn + 255) / 256, 8192), s);
+        L::event_inject(t1, (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192)),
+                        ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
+        if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) L::beta_dots(t1, ins[m].nblk_st, s);
+    };
+    const std::vector<std::pair<int, const DevEvent*>> no_mid;
+    // replay `chunk` steps from the graph of this launch-table shape
+    // (captured first when the shape is new)
+    auto replay = [&]() -> ftgcr_status {
+        const long long key[8] = {sh.n, sh.cols, sh.sts, sh.dirs, kc, H, nt_ap ? 1 : 0, chunk};
+        if (!B.graph || std::memcmp(key, B.graph_key, sizeof key) != 0) {
+            if (B.graph) {
+                (void)hipGraphExecDestroy(B.graph);
+                B.graph = nullptr;
+            }
+            HIP_TRY(h0, hipStreamBeginCapture(h0->cap_stream, hipStreamCaptureModeRelaxed));
+            for (int q = 0; q < chunk; ++q) batch_step(tb, sh, H, kc, nt_ap, h0->cap_stream, no_mid, apply);
+            hipGraph_t g = nullptr;
+            HIP_TRY(h0, hipStreamEndCapture(h0->cap_stream, &g));
+            const hipError_t e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                B.graph = nullptr;
+                return fail(h0, FTGCR_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            std::memcpy(B.graph_key, key, sizeof key);
+        }
+        HIP_TRY(h0, hipGraphLaunch(B.graph, s));
+        return FTGCR_OK;
+    };
     while (!members.empty()) {
         // fault events of the next step, member by member: x, r, p, L(p)
         // events now, e events between the step's decision and its stencil
         // pass
-        auto apply = [&](int m, const DevEvent& ev) {
-            const Table<double> t1 = single(m);
-            const long long nn = hs[m]->geo.n;
-            L::event_prep(t1, ev.vec, s);
-            if (ev.vec != FTGCR_V_E) L::event_copy(t1, (int)std::min<long long>((nn + 255) / 256, 8192), s);
-            L::event_inject(t1, (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192)),
-                            ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
-            if (ev.vec == FTGCR_V_R || ev.vec == FTGCR_V_AP) L::beta_dots(t1, ins[m].nblk_st, s);
-        };
         bool any_event = false;
         std::vector<std::pair<int, const DevEvent*>> mid;
         for (int m : members) {
@@ -886,76 +968,54 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         long long cnt = any_event ? 1 : chunk;
         for (int m : members)
             if (evp[m] < evs[m].size()) cnt = std::min<long long>(cnt, std::max<long long>(1, evs[m][evp[m]].step - 1 - launched));
-        for (long long q = 0; q < cnt; ++q) {
-            L::update_thomas(tb, bt.cols, H, 0, s);
-            if (!mid.empty()) {   // cnt == 1 whenever mid is not empty
-                L::finish_col(tb, 0, s);
-                for (const auto& me : mid) apply(me.first, *me.second);
-                L::stencil_dots(tb, bt.sts, kc, 0, s);
-                L::finish_alpha(tb, s);
-            } else {
-                L::stencil_dots(tb, bt.sts, kc, 1, s);
-                L::finish_step(tb, s);
-            }
-            L::dir_update(tb, bt.dirs, kc < 4 ? kc : 4, 0, nt_ap, s);
-            L::finish_beta(tb, 0, s);
+        if (cnt == chunk && !any_event && h0->opt.use_graphs) {
+            rc = replay();
+            if (rc != FTGCR_OK) return rc;
+        } else {
+            for (long long q = 0; q < cnt; ++q) batch_step(tb, sh, H, kc, nt_ap, s, mid, apply);   // cnt == 1 if mid
         }
         launched += cnt;
-        L::gather_status(tb, bt.status, s);
-        if (hipMemcpyAsync(host_status.data(), bt.status, 2 * members.size() * sizeof(long long),
+        L::gather_status(tb, B.status, s);
+        if (hipMemcpyAsync(host_status.data(), B.status, 2 * members.size() * sizeof(long long),
                            hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            cleanup_full();
+            hipStreamSynchronize(s) != hipSuccess)
             return fail(h0, FTGCR_E_HIP, "batch status read failed");
-        }
         std::vector<int> still;
-        for (size_t q = 0; q < members.size(); ++q)
+        long long done_blocks = 0;
+        for (size_t q = 0; q < members.size(); ++q) {
             if (host_status[2 * q] == RUNNING) still.push_back(members[q]);
-        if (still.size() != members.size()) {
+            else done_blocks += ins[members[q]].nblk_st;
+        }
+        if (still.empty()) break;
+        if (8 * done_blocks >= sh.sts) {
             members.swap(still);
-            if (!members.empty()) {
-                rc = upload_batch(h0, ins, members, bt, tb);
-                if (rc != FTGCR_OK) {
-                    cleanup_full();
-                    return rc;
-                }
-            }
+            rc = upload_batch(h0, ins, members, B.inst, B.blk0, sh, tb);
+            if (rc != FTGCR_OK) return rc;
         }
-        if (launched > max_cap + chunk + 16) {
-            cleanup_full();
-            return fail(h0, FTGCR_E_HIP, "batched step loop did not terminate");
-        }
+        if (launched > max_cap + chunk + 16) return fail(h0, FTGCR_E_HIP, "batched step loop did not terminate");
     }
-    L::finalize_x(tb_all, sts_all, kc, s);
-    L::residual(tb_all, sts_all, kc, 0, 0, s);
+    L::finalize_x(tb_all, sh_all.sts, kc, s);
+    L::residual(tb_all, sh_all.sts, kc, 0, 0, s);
     (void)hipEventRecord(e1, s);
-    if (hipStreamSynchronize(s) != hipSuccess) {
-        cleanup_full();
-        return fail(h0, FTGCR_E_HIP, "batch synchronisation failed");
-    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(h0, FTGCR_E_HIP, "batch synchronisation failed");
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     for (int m = 0; m < n; ++m) {
         ftgcr_handle* h = hs[m];
-        if (hipMemcpy(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost) != hipSuccess) {
-            cleanup_full();
+        if (hipMemcpy(h->st_host, h->st, sizeof(SolveState), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(h0, FTGCR_E_HIP, "batch state read failed");
-        }
         if (stats) {
             fill_stats(h, *h->st_host, 0, ms, &stats[m]);
             if (stats[m].hist && stats[m].hist_cap > 0) {
                 const long long nh = std::min<long long>(std::min<long long>(h->st_host->s, h->opt.hist_cap),
                                                          stats[m].hist_cap);
                 if (nh > 0 && hipMemcpy(stats[m].hist, ins[m].hist, (size_t)nh * sizeof(double),
-                                        hipMemcpyDeviceToHost) != hipSuccess) {
-                    cleanup_full();
+                                        hipMemcpyDeviceToHost) != hipSuccess)
                     return fail(h0, FTGCR_E_HIP, "batch history read failed");
-                }
                 stats[m].hist_len = nh;
             }
         }
     }
-    cleanup_full();
     return FTGCR_OK;
 }
 
@@ -1100,8 +1160,8 @@ ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev, 
     if (!h->ws) return fail(h, FTGCR_E_WORKSPACE, "no workspace set");
     if (h->ws_bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "workspace smaller than required by the current options");
     HIP_TRY(h, hipSetDevice(h->device));
-    if (h->precision == FTGCR_MIXED) return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats);
-    return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats);
+    if (h->precision == FTGCR_MIXED) return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
+    return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
 }
 
 ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double* const* rhs, double* const* x,
@@ -1284,7 +1344,44 @@ void ftgcr_destroy(ftgcr_handle* h)
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
     if (h->ev_idx) (void)hipFree(h->ev_idx);
     if (h->ev_bits) (void)hipFree(h->ev_bits);
+    if (h->batch.graph) (void)hipGraphExecDestroy(h->batch.graph);
+    (void)hipFree(h->batch.inst);
+    (void)hipFree(h->batch.blk0);
+    (void)hipFree(h->batch.status);
+    (void)hipFree(h->batch.all);
+    (void)hipFree(h->batch.blk0_all);
     delete h;
+}
+
+ftgcr_status ftgcr_bw_probe(const void* src_dev, void* dst_dev, size_t bytes, int32_t reps, void* hip_stream,
+                            double* gbs)
+{
+    if (!src_dev || !dst_dev || !gbs) return fail(nullptr, FTGCR_E_INVALID, "src, dst or gbs is NULL");
+    if (bytes == 0 || (bytes & 15) != 0 || reps < 1)
+        return fail(nullptr, FTGCR_E_INVALID, "bytes must be a positive multiple of 16 and reps >= 1");
+    if ((((uintptr_t)src_dev) | ((uintptr_t)dst_dev)) & 15)
+        return fail(nullptr, FTGCR_E_INVALID, "src and dst must be 16-byte aligned");
+    const uintptr_t s0 = (uintptr_t)src_dev, d0 = (uintptr_t)dst_dev;
+    if (s0 < d0 + bytes && d0 < s0 + bytes) return fail(nullptr, FTGCR_E_INVALID, "src and dst overlap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(nullptr, FTGCR_E_HIP, "hipEventCreate failed");
+    }
+    launch_bw_copy(src_dev, dst_dev, (long long)bytes, s);   // warm-up
+    hipError_t e = hipEventRecord(e0, s);
+    for (int q = 0; q < reps && e == hipSuccess; ++q) launch_bw_copy(src_dev, dst_dev, (long long)bytes, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(nullptr, FTGCR_E_HIP, std::string("bandwidth probe: ") + hipGetErrorString(e));
+    *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return FTGCR_OK;
 }
 
 const char* ftgcr_last_error(const ftgcr_handle* h)

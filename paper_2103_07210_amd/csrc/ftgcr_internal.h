@@ -179,6 +179,10 @@ template <typename T> struct Launch {
     static void debug_pinv(const Table<T>& tb, int total_col_blocks, int H, const double* in, double* out, hipStream_t s);
 };
 
+// Plain streaming copy of `bytes` (a multiple of 16, 16-byte aligned
+// pointers): the bandwidth probe.
+void launch_bw_copy(const void* src, void* dst, long long bytes, hipStream_t s);
+
 // Smallest supported register-array depth H >= levels per column half.
 int thomas_depth(int nz);
 

@@ -1915,4 +1915,40 @@ void Launch<T>::gather_status(const Table<T>& tb, long long* out, hipStream_t s)
 template struct Launch<double>;
 template struct Launch<float>;
 
+// ---------------------------------------------------------------------------
+// bandwidth probe: a plain streaming copy, the reference for what a kernel
+// that reads and writes each byte once can reach on this device
+// ---------------------------------------------------------------------------
+
+// Each thread moves COPY_UNROLL 16-byte vectors, a block's vectors
+// contiguous per unrolled step (full 1 KiB wave segments); all loads of a
+// thread are issued before its first store.
+constexpr int COPY_UNROLL = 4;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_bw_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                 long long nvec)
+{
+    const long long base = (long long)blockIdx.x * (256 * COPY_UNROLL) + threadIdx.x;
+    u32x4 v[COPY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+        const long long q = base + (long long)u * 256;
+        const long long qc = q < nvec ? q : nvec - 1;   // clamped: branch-free loads
+        v[u] = __builtin_nontemporal_load(&src[qc]);
+    }
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+        const long long q = base + (long long)u * 256;
+        if (q < nvec) __builtin_nontemporal_store(v[u], &dst[q]);
+    }
+}
+
+void launch_bw_copy(const void* src, void* dst, long long bytes, hipStream_t s)
+{
+    const long long nvec = bytes / 16;
+    const long long blocks = (nvec + 256 * COPY_UNROLL - 1) / (256 * COPY_UNROLL);
+    hipLaunchKernelGGL(k_bw_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, nvec);
+}
+
 }  // namespace ftgcr

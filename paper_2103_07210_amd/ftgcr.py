@@ -28,7 +28,7 @@ EXPORTED = ["ftgcr_default_options", "ftgcr_create", "ftgcr_set_options", "ftgcr
             "ftgcr_set_stream", "ftgcr_workspace_bytes", "ftgcr_set_workspace", "ftgcr_solve",
             "ftgcr_solve_batch", "ftgcr_destroy", "ftgcr_last_error", "ftgcr_debug_apply_A",
             "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times", "ftgcr_autotune",
-            "ftgcr_autotune_batch"]
+            "ftgcr_autotune_batch", "ftgcr_bw_probe"]
 
 
 class FtgcrError(RuntimeError):
@@ -141,6 +141,8 @@ def load():
     lib.ftgcr_autotune_batch.argtypes = [ctypes.POINTER(H), ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.ftgcr_autotune_batch.restype = ctypes.c_int
+    lib.ftgcr_bw_probe.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.ftgcr_bw_probe.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -267,6 +269,7 @@ class Solver:
         contiguous FP64 device tensor."""
         import torch
         lib = load()
+        entry = lib.ftgcr_solve
         rhs_t = self._dev(rhs)
         if x is None:
             x_t = torch.zeros_like(rhs_t)
@@ -281,8 +284,8 @@ class Solver:
         st.hist_cap = hist_cap
         st.hist = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         lib.ftgcr_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-        _check(lib.ftgcr_solve(self._h, ctypes.c_void_p(rhs_t.data_ptr()), ctypes.c_void_p(x_t.data_ptr()),
-                               float(tol), int(k), ctypes.byref(ph.plan) if plan else None, ctypes.byref(st)),
+        _check(entry(self._h, ctypes.c_void_p(rhs_t.data_ptr()), ctypes.c_void_p(x_t.data_ptr()),
+                     float(tol), int(k), ctypes.byref(ph.plan) if plan else None, ctypes.byref(st)),
                self._h)
         return x_t, _stats_out(st, log, hist if hist_cap > 0 else None)
 
@@ -364,6 +367,21 @@ def solve_batch(solvers: Sequence[Solver], rhs: Sequence, xs: Optional[Sequence]
         S[m].log = ctypes.cast(logs[m], ctypes.POINTER(DetectRec))
     _check(lib.ftgcr_solve_batch(H, n, R, X, T, int(k), P if plans else None, S), solvers[0]._h)
     return xs_t, [_stats_out(S[m], logs[m], None) for m in range(n)]
+
+
+def bw_probe(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """HBM copy bandwidth (read + write, GB/s) of the library's streaming
+    copy kernel over two fresh device buffers of `nbytes` each."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    gbs = ctypes.c_double()
+    _check(load().ftgcr_bw_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                 src.numel() * 8, int(reps),
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(gbs)))
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst), "bandwidth probe copied wrong data"
+    return gbs.value
 
 
 def autotune_batch(solvers: Sequence[Solver], rhs: Sequence, k: int = 3, steps: int = 24) -> int:

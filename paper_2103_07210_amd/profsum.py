@@ -2,15 +2,16 @@
 kept under profiles/.
 
   python -m paper_2103_07210_amd.profsum stats  <rocprof out dir> <cmd> > profiles/<name>.md
-  python -m paper_2103_07210_amd.profsum pmc    <fetch out dir> <write out dir> <cmd> > profiles/<name>.md
+  python -m paper_2103_07210_amd.profsum pmc    <fetch out dir> <write out dir> <grid> <cmd> > profiles/<name>.md
 
 `stats` reads the kernel-trace CSV (or the rocpd SQLite database) and lists,
 per kernel, dispatches, total and average duration, and the average over
 dispatches longer than 20 us (launches enqueued after a solve converged
 return at once and would bias the average).  `pmc` reads two counter runs
 (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) and reports the per-launch average
-for the FP64 dir_update kernel and the device copy kernel of the 1 GiB
-calibration copy, whose known size gives the scale factor.
+for the FP64 dir_update kernel and the library's bandwidth-probe copy kernel
+(k_bw_copy) of the 1 GiB calibration copy, whose known size gives the scale
+factor.
 """
 import csv
 import glob
@@ -68,7 +69,7 @@ def _counters(outdir, counter):
     return per
 
 
-def pmc(fetch_dir, write_dir, cmd):
+def pmc(fetch_dir, write_dir, grid, cmd):
     fetch = _counters(fetch_dir, "FETCH_SIZE")
     write = _counters(write_dir, "WRITE_SIZE")
     copy_bytes = float(1 << 30)
@@ -84,11 +85,11 @@ def pmc(fetch_dir, write_dir, cmd):
 
     f_dir, nf = avg_big(pick(fetch, "k_dir_update<double"))
     w_dir, nw = avg_big(pick(write, "k_dir_update<double"))
-    f_cp, _ = avg_big(pick(fetch, "copyBuffer"))
-    w_cp, _ = avg_big(pick(write, "copyBuffer"))
+    f_cp, _ = avg_big(pick(fetch, "k_bw_copy"))
+    w_cp, _ = avg_big(pick(write, "k_bw_copy"))
     sf = copy_bytes / (f_cp * 1024.0) if f_cp else 0.0
     sw = copy_bytes / (w_cp * 1024.0) if w_cp else 0.0
-    print("# rocprofv3 HBM traffic counters, FP64 dir_update on 512x256x64\n")
+    print(f"# rocprofv3 HBM traffic counters, FP64 dir_update on {grid}\n")
     print(f"command (two passes, FETCH_SIZE then WRITE_SIZE): `{cmd}`\n")
     print(f"kernels_hip_sha256: {source_sha256()}")
     print(f"dir_update_fetch_kib_per_launch: {f_dir:.1f}")
@@ -125,4 +126,4 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "pmc":
-        pmc(sys.argv[2], sys.argv[3], sys.argv[4])
+        pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])

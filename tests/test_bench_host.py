@@ -16,15 +16,38 @@ N = 512 * 256 * 64
 
 
 def test_alg_bytes_per_pass():
-    """One cycle of k = 4 steps plus the converging step: column pass 4 s N
-    per step; dots (nu + 2) s N and direction pass (2 nu + 6) s N (+ the
-    iterate, 2 * 8 N, at nu = k - 1) on every step but the last."""
+    """One cycle of k = 4 steps plus the converging step.  Algorithmic bytes
+    of the direction pass: the direction phase (2 nu + 5) s N plus the
+    iterate (2 * 8 N) at nu = k - 1; the design's own kernels: column pass
+    4 s N, dots (nu + 2) s N, direction pass (2 nu + 6) s N (+ the iterate),
+    the last step running the column pass only."""
     steps, k, s = 5, 4, 8
-    assert bench.alg_bytes("update_thomas", steps, k, N, s) == 5 * 4 * s * N
-    assert bench.alg_bytes("stencil_dots", steps, k, N, s) == (2 + 3 + 4 + 5) * s * N
-    assert bench.alg_bytes("dir_update", steps, k, N, s) == (6 + 8 + 10 + 12) * s * N + 16 * N
+    assert bench.alg_bytes("dir_update", steps, k, N, s) == (5 + 7 + 9 + 11) * s * N + 16 * N
+    assert bench.alg_bytes("update_thomas", steps, k, N, s, design=True) == 5 * 4 * s * N
+    assert bench.alg_bytes("stencil_dots", steps, k, N, s, design=True) == (2 + 3 + 4 + 5) * s * N
+    assert bench.alg_bytes("dir_update", steps, k, N, s, design=True) == (6 + 8 + 10 + 12) * s * N + 16 * N
     # binary32 vectors with the FP64 iterate
-    assert bench.alg_bytes("dir_update", steps, k, N, 4) == (6 + 8 + 10 + 12) * 4 * N + 16 * N
+    assert bench.alg_bytes("dir_update", steps, k, N, 4) == (5 + 7 + 9 + 11) * 4 * N + 16 * N
+
+
+def test_solve_bytes_model():
+    """A whole solve: W(nu) = (3 nu + 11) s N per step (the converging step
+    only its update phase, nu + 6), 4 s N of backup per cycle, 6 s N for the
+    start of each round and 3 * 8 N per FP64 true-residual pass; at k = 4 a
+    step averages 16.5 sweeps and the design moves 17 (e stored and re-read,
+    the iterate once per cycle)."""
+    k, s = 4, 8
+    steps = 4 * 100 + 1
+    alg = bench.solve_bytes(steps, k, N, s)
+    per_cycle = sum(3 * nu + 11 for nu in range(4)) + 4
+    expect = 100 * per_cycle * s * N + (6 + 4) * s * N + 6 * s * N + 24 * N
+    assert alg == expect
+    des = bench.solve_bytes(steps, k, N, s, design=True)
+    assert des == 100 * (4 * 4 + (2 + 3 + 4 + 5) + (6 + 8 + 10 + 12)) * s * N + 100 * 16 * N + 4 * s * N \
+        + 6 * s * N + 24 * N
+    fr = bench.step_frac(steps, k, N, s, ms=100.0)
+    assert abs(fr["alg_gbs"] - alg / 0.1 / 1e9) < 1e-6 and abs(fr["frac"] - fr["alg_gbs"] / 8000.0) < 1e-12
+    assert 0.02 < fr["design_overhead"] < 0.04
 
 
 def test_alg_bytes_sampled_steps():
@@ -35,7 +58,7 @@ def test_alg_bytes_sampled_steps():
     full = bench.alg_bytes("dir_update", steps, k, N, s)
     samp = bench.alg_bytes("dir_update", steps, k, N, s, stride=5)
     n_samp = len([t for t in range(1, steps) if t % 5 == 0])
-    assert samp == sum((2 * ((t - 1) % k) + 6) * s * N + (16 * N if (t - 1) % k == k - 1 else 0)
+    assert samp == sum((2 * ((t - 1) % k) + 5) * s * N + (16 * N if (t - 1) % k == k - 1 else 0)
                        for t in range(5, steps, 5))
     assert abs(samp / n_samp - full / (steps - 1)) < 0.01 * full / (steps - 1)
     assert bench.TIMED_STRIDE % 2 and bench.TIMED_STRIDE % bench.K
