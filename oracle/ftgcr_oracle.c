@@ -422,3 +422,253 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
     free(pool); free(d); free(alpha);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* FT-GMRES(k): the same fault-tolerance layer on restarted GMRES.            */
+/* ------------------------------------------------------------------------- */
+/*
+ * The paper presents its detector as compatible with other Krylov solvers
+ * (abstract; Section 1 contrasts it with FT-GMRES, which bounds Hessenberg
+ * entries instead).  Here the residual-norm test, the backup of a known-good
+ * state after each complete Krylov cycle and the rollback of Algorithm 1
+ * (red part) wrap right-preconditioned restarted GMRES(k):
+ *
+ *   cycle:  s = R - A x, rho = |s|, v_0 = s / rho, g = (rho, 0, ...)
+ *     step j = 0..k-1:  z_j = P^{-1} v_j;  w = A z_j;
+ *                       h_ij = <w, v_i> (i <= j, classical Gram-Schmidt);
+ *                       w -= sum_i h_ij v_i (ascending i);  h_{j+1,j} = |w|;
+ *                       rotate column j by the earlier Givens rotations, form
+ *                       the rotation that zeroes h_{j+1,j}, apply it to g;
+ *                       the step's residual norm is |g_{j+1}| (the norm of
+ *                       R - A (x + sum y_i z_i) minimised over the cycle);
+ *                       exit test, then fault test !(g_{j+1}^2 < g_j^2);
+ *                       v_{j+1} = w / h_{j+1,j}
+ *     end:   y = H^{-1} g (upper triangular, the steps done), x += sum y_i z_i
+ *            (ascending i), then the explicit residual s = R - A x: exit if
+ *            |s|^2 <= tol^2 |R|^2, fault if !(|s|^2 < the cycle start's),
+ *            else the new backup [x, |s|^2].
+ *
+ * A fault test that fires inside a cycle or at its end restores x and |s|^2
+ * from the backup and restarts the cycle from the residual of the restored x
+ * (inside a cycle x is not yet changed, so only the Krylov basis is lost).
+ * The stagnation rule is that of FT-GCR: a detection at the same place after
+ * a rollback with no fault event since is accepted.  Places are numbered
+ * 2 (accepted + 1) for a step and 2 accepted + 1 for a cycle-end check.
+ * Fault events: X flips x at the start of the step, R flips v_j at the start
+ * of the step (before P^{-1} reads it), P and E flip z_j = P^{-1} v_j right
+ * after the preconditioner, AP flips w = A z_j before the inner products.
+ * The residual history holds g_{j+1}^2 per executed step; a cycle-end
+ * detection is logged with nu = -1 and the explicit squared norms.
+ */
+
+static void residual_RAx(const orc_problem* pb, const double* wx, const double* wy, const double* wz,
+                         const double* rhs, const double* x, double* s, int64_t n)
+{
+    orc_apply_A(pb, wx, wy, wz, x, s);
+    for (int64_t t = 0; t < n; ++t) s[t] = rhs[t] - s[t];
+}
+
+static void log_detection(orc_stats* st, orc_detect* log, int32_t log_cap, int64_t step, int nu, int action,
+                          double rr_old, double rr_new)
+{
+    st->detections += 1;
+    if (log && st->log_len < log_cap) {
+        orc_detect* rec = &log[st->log_len++];
+        rec->step = step; rec->nu = nu; rec->action = action;
+        rec->rr_old = rr_old; rec->rr_new = rr_new;
+    }
+}
+
+static void apply_events_at(const orc_event* events, int32_t n_events, int64_t step, int vec_a, int vec_b,
+                            double* target, orc_stats* st, int* events_since_rb)
+{
+    for (int32_t q = 0; q < n_events; ++q) {
+        if (events[q].step != step || (events[q].vec != vec_a && events[q].vec != vec_b)) continue;
+        apply_event(&events[q], target);
+        st->events_applied += 1;
+        *events_since_rb = 1;
+    }
+}
+
+int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double tol,
+                    int32_t k, int64_t max_steps, int32_t ft,
+                    const orc_event* events, int32_t n_events, orc_stats* st,
+                    orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
+{
+    if (!pb || !rhs || !x || !st || k < 1 || !(tol > 0.0) || max_steps < 0) return -1;
+    if (pb->nx < 3 || pb->ny < 1 || pb->nz < 1) return -1;
+    const int64_t n = (int64_t)pb->nx * pb->ny * pb->nz;
+    for (int32_t q = 0; q < n_events; ++q) {
+        const orc_event* ev = &events[q];
+        if (ev->vec < ORC_V_X || ev->vec > ORC_V_E || ev->count < 0) return -1;
+        for (int64_t t = 0; t < ev->count; ++t) {
+            int64_t at = ev->idx ? ev->idx[t] : ev->start + t;
+            int bit = ev->bits ? (int)ev->bits[t] : (int)ev->bit;
+            if (at < 0 || at >= n || bit < 0 || bit > 63) return -1;
+        }
+    }
+    memset(st, 0, sizeof *st);
+    const int64_t nwx = n, nwy = (int64_t)pb->nx * (pb->ny + 1) * pb->nz,
+                  nwz = (int64_t)pb->nx * pb->ny * (pb->nz + 1);
+    /* s, w, the backup of x, v_0..v_k, z_0..z_{k-1} */
+    const int64_t nvec = 3 + (k + 1) + k;
+    double* pool = (double*)malloc(sizeof(double) * (size_t)(nwx + nwy + nwz + nvec * n));
+    double* hh = (double*)calloc((size_t)(k + 1) * k, sizeof(double));   /* H[i][j] = hh[i*k + j] */
+    double* cs = (double*)calloc((size_t)k, sizeof(double));
+    double* sn = (double*)calloc((size_t)k, sizeof(double));
+    double* g = (double*)calloc((size_t)k + 1, sizeof(double));
+    double* y = (double*)calloc((size_t)k, sizeof(double));
+    if (!pool || !hh || !cs || !sn || !g || !y) {
+        free(pool); free(hh); free(cs); free(sn); free(g); free(y);
+        return -1;
+    }
+    double* wx = pool;
+    double* wy = wx + nwx;
+    double* wz = wy + nwy;
+    double* s = wz + nwz;
+    double* w = s + n;
+    double* xb = w + n;
+    double* V = xb + n;                  /* v_i = V + i*n, i = 0..k  */
+    double* Z = V + (int64_t)(k + 1) * n; /* z_i = Z + i*n, i < k    */
+    orc_face_weights(pb, wx, wy, wz);
+
+    const double RR = orc_dot(n, rhs, rhs);
+    const double T = tol * tol * RR;
+    st->rhs_norm2 = RR;
+    residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+    double rho2 = orc_dot(n, s, s);
+    int status = -1;
+    if (rho2 <= T) status = ORC_CONVERGED;
+    /* the initial state is the first known-good state */
+    copy_vec(n, x, xb);
+    double b_rho2 = rho2;
+    int64_t b_accepted = 0;
+    int64_t sx = 0, accepted = 0;
+    int64_t last_rb_pos = -1;
+    int events_since_rb = 1;
+
+    while (status < 0) {
+        /* a new cycle from the residual s of x */
+        const double rho = sqrt(rho2);
+        for (int64_t t = 0; t < n; ++t) V[t] = s[t] / rho;
+        for (int i = 0; i <= k; ++i) g[i] = 0.0;
+        g[0] = rho;
+        double rr_old = rho2;
+        int jdone = 0, rolled = 0, capped = 0;
+        for (int j = 0; j < k; ++j) {
+            double* vj = V + (int64_t)j * n;
+            double* zj = Z + (int64_t)j * n;
+            if (sx >= max_steps) { capped = 1; break; }
+            sx += 1;
+            if (j == 0) st->cycles += 1;
+            apply_events_at(events, n_events, sx, ORC_V_X, ORC_V_X, x, st, &events_since_rb);
+            apply_events_at(events, n_events, sx, ORC_V_R, ORC_V_R, vj, st, &events_since_rb);
+            orc_apply_pinv(pb, wx, wy, wz, vj, zj);
+            apply_events_at(events, n_events, sx, ORC_V_P, ORC_V_E, zj, st, &events_since_rb);
+            orc_apply_A(pb, wx, wy, wz, zj, w);
+            apply_events_at(events, n_events, sx, ORC_V_AP, ORC_V_AP, w, st, &events_since_rb);
+            for (int i = 0; i <= j; ++i) hh[i * k + j] = orc_dot(n, w, V + (int64_t)i * n);
+            for (int i = 0; i <= j; ++i) {
+                const double* vi = V + (int64_t)i * n;
+                const double hij = hh[i * k + j];
+                for (int64_t t = 0; t < n; ++t) w[t] = w[t] - hij * vi[t];
+            }
+            const double hn = sqrt(orc_dot(n, w, w));
+            hh[(j + 1) * k + j] = hn;
+            /* earlier rotations on column j, then the new one */
+            for (int i = 0; i < j; ++i) {
+                const double a = hh[i * k + j], b = hh[(i + 1) * k + j];
+                hh[i * k + j] = cs[i] * a + sn[i] * b;
+                hh[(i + 1) * k + j] = -sn[i] * a + cs[i] * b;
+            }
+            {
+                const double a = hh[j * k + j], b = hh[(j + 1) * k + j];
+                const double den = sqrt(a * a + b * b);
+                cs[j] = a / den;
+                sn[j] = b / den;
+                hh[j * k + j] = den;
+                hh[(j + 1) * k + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+            }
+            const double rr_new = g[j + 1] * g[j + 1];
+            if (hist && sx <= hist_cap) hist[sx - 1] = rr_new;
+            jdone = j + 1;
+            /* exit test first, then the fault test */
+            if (rr_new <= T) { accepted += 1; rr_old = rr_new; break; }
+            if (ft && !(rr_new < rr_old)) {
+                const int64_t pos = 2 * (accepted + 1);
+                const int stag = (pos == last_rb_pos) && !events_since_rb;
+                log_detection(st, log, log_cap, sx, j, stag, rr_old, rr_new);
+                if (!stag) {
+                    copy_vec(n, xb, x);
+                    accepted = b_accepted;
+                    last_rb_pos = pos;
+                    events_since_rb = 0;
+                    rolled = 1;
+                    break;
+                }
+                st->stagnation_accepts += 1;
+            }
+            accepted += 1;
+            rr_old = rr_new;
+            if (hn == 0.0) break;   /* the cycle's space holds the solution */
+            double* vn = V + (int64_t)(j + 1) * n;
+            for (int64_t t = 0; t < n; ++t) vn[t] = w[t] / hn;
+        }
+        if (rolled) {
+            residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+            rho2 = orc_dot(n, s, s);
+            continue;
+        }
+        /* the cycle's correction: H y = g over the steps done, x += sum y_i z_i */
+        for (int i = jdone - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int l = i + 1; l < jdone; ++l) acc = acc - hh[i * k + l] * y[l];
+            y[i] = acc / hh[i * k + i];
+        }
+        for (int i = 0; i < jdone; ++i) {
+            const double* zi = Z + (int64_t)i * n;
+            for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y[i] * zi[t];
+        }
+        residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+        const double rho2_new = orc_dot(n, s, s);
+        if (capped || (sx >= max_steps && rho2_new > T)) {
+            rho2 = rho2_new;
+            status = ORC_MAX_STEPS;
+            break;
+        }
+        if (rho2_new <= T) { rho2 = rho2_new; status = ORC_CONVERGED; break; }
+        if (ft && !(rho2_new < b_rho2)) {
+            const int64_t pos = 2 * accepted + 1;
+            const int stag = (pos == last_rb_pos) && !events_since_rb;
+            log_detection(st, log, log_cap, sx, -1, stag, b_rho2, rho2_new);
+            if (!stag) {
+                copy_vec(n, xb, x);
+                accepted = b_accepted;
+                last_rb_pos = pos;
+                events_since_rb = 0;
+                residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+                rho2 = orc_dot(n, s, s);
+                continue;
+            }
+            st->stagnation_accepts += 1;
+        }
+        /* the cycle passed: its output is the new known-good state */
+        if (ft) {
+            copy_vec(n, x, xb);
+            b_rho2 = rho2_new;
+            b_accepted = accepted;
+        }
+        rho2 = rho2_new;
+    }
+    st->status = status;
+    st->steps_executed = sx;
+    st->steps_accepted = accepted;
+    st->steps_wasted = sx - accepted;
+    st->rr_final = rho2;
+    st->rel_res_recursive = RR > 0.0 ? sqrt(rho2 / RR) : 0.0;
+    st->hist_len = sx < hist_cap ? sx : hist_cap;
+    free(pool); free(hh); free(cs); free(sn); free(g); free(y);
+    return 0;
+}

@@ -136,6 +136,19 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
                      orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap,
                      double* cos_r_ap, double* cos_ap, int64_t trace_cap);
 
+/* FT-GMRES(k): right-preconditioned restarted GMRES(k) with the same fault
+ * layer (the residual-norm test after every step and at the end of every
+ * cycle, the backup [x, |R - A x|^2] after each cycle that passes, the
+ * rollback and the stagnation rule); see the comment above its definition.
+ * Arguments, outcomes and the log as for orc_solve (a cycle-end detection
+ * has nu = -1); tol is relative: stop when |R - A x|^2 <= tol^2 |R|^2 on
+ * the explicit residual at a cycle end.  hist gets the step's squared
+ * residual norm |g_{j+1}|^2 of the Arnoldi least-squares problem. */
+int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double tol,
+                    int32_t k, int64_t max_steps, int32_t ft,
+                    const orc_event* events, int32_t n_events, orc_stats* st,
+                    orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,14 @@ Functions and what pins them (tests/test_oracle_*.py):
   solve (Algorithm 1) -- dense LU solutions, right-preconditioned GMRES
       residual norms for a single long cycle, GCR orthogonality invariants,
       and predicted fault outcomes (detected transient fault reproduces the
-      fault-free solution bit for bit; x and p faults never reach r).
+      fault-free solution bit for bit; x and p faults never reach r);
+  solve(method='gmres') (FT-GMRES(k), the same fault layer on restarted
+      GMRES) -- per-step residual norms of an independent dense restarted
+      GMRES (QR of the power Krylov basis, least squares) over several
+      cycles, GCR(k) on one long cycle, dense LU solutions, and predicted
+      fault outcomes (x flips caught at the cycle end, overflowing v or
+      A z flips at their step, both recovered bit for bit; flips of z are
+      consistent with A z and never detected).
 """
 from __future__ import annotations
 
@@ -89,6 +96,8 @@ def _load():
         lib.orc_solve.restype = ctypes.c_int
         lib.orc_solve_traced.argtypes = lib.orc_solve.argtypes + [dp, dp, ctypes.c_int64]
         lib.orc_solve_traced.restype = ctypes.c_int
+        lib.orc_gmres_solve.argtypes = lib.orc_solve.argtypes
+        lib.orc_gmres_solve.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -173,10 +182,13 @@ class Oracle:
 
     def solve(self, rhs, x0=None, tol: float = 1e-10, k: int = 3, max_steps: int = 100000,
               ft: bool = True, plan: Optional[Sequence] = None, log_cap: int = 4096,
-              hist_cap: Optional[int] = None, trace: bool = False):
-        """Run FT-GCR(k).  Returns (x, stats dict, detection log, rr history).
-        With trace=True the stats also hold the per-step orthogonality
-        diagnostics 'cos_r_ap' and 'cos_ap' (see orc_solve_traced)."""
+              hist_cap: Optional[int] = None, trace: bool = False, method: str = "gcr"):
+        """Run FT-GCR(k) (method 'gcr') or FT-GMRES(k) ('gmres').  Returns
+        (x, stats dict, detection log, rr history).  With trace=True (GCR
+        only) the stats also hold the per-step orthogonality diagnostics
+        'cos_r_ap' and 'cos_ap' (see orc_solve_traced)."""
+        if method not in ("gcr", "gmres") or (trace and method != "gcr"):
+            raise ValueError("method is 'gcr' or 'gmres'; trace is for 'gcr'")
         rhs = _vec(rhs, self.n)
         x = np.zeros(self.n) if x0 is None else _vec(x0, self.n).copy()
         plan = list(plan or [])
@@ -209,11 +221,17 @@ class Oracle:
         st = _Stats()
         cos_r_ap = np.zeros(max(1, hist_cap)) if trace else None
         cos_ap = np.zeros(max(1, hist_cap)) if trace else None
-        rc = _load().orc_solve_traced(
-            ctypes.byref(self._c), _ptr(rhs), _ptr(x), float(tol), int(k), int(max_steps),
-            1 if ft else 0, events, len(plan), ctypes.byref(st), log, int(log_cap),
-            _ptr(hist), int(hist_cap), _ptr(cos_r_ap) if trace else None,
-            _ptr(cos_ap) if trace else None, int(hist_cap) if trace else 0)
+        if method == "gmres":
+            rc = _load().orc_gmres_solve(
+                ctypes.byref(self._c), _ptr(rhs), _ptr(x), float(tol), int(k), int(max_steps),
+                1 if ft else 0, events, len(plan), ctypes.byref(st), log, int(log_cap),
+                _ptr(hist), int(hist_cap))
+        else:
+            rc = _load().orc_solve_traced(
+                ctypes.byref(self._c), _ptr(rhs), _ptr(x), float(tol), int(k), int(max_steps),
+                1 if ft else 0, events, len(plan), ctypes.byref(st), log, int(log_cap),
+                _ptr(hist), int(hist_cap), _ptr(cos_r_ap) if trace else None,
+                _ptr(cos_ap) if trace else None, int(hist_cap) if trace else 0)
         if rc != 0:
             raise ValueError("oracle rejected the arguments")
         stats = {name: getattr(st, name) for name, _ in _Stats._fields_ if name != "pad_"}
