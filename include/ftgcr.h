@@ -209,6 +209,24 @@ ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev,
                          double tol, int32_t k, const ftgcr_fault_plan* plan,
                          ftgcr_stats* stats);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  As ftgcr_solve, but the working vectors and the fault plan's
+ * entry lists live in a device scratch array of FTGCR_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process ends,
+ * not in the workspace of ftgcr_set_workspace (none need be set).  Limit:
+ * ftgcr_workspace_bytes(h) rounded up to 256, plus 9 bytes per fault-plan
+ * entry given as an index list, must fit the scratch; otherwise the call
+ * returns FTGCR_E_WORKSPACE with a message and runs nothing.  The call
+ * allocates nothing (no hipMalloc, hipFree, graph or event creation):
+ * options.use_graphs and options.profile_kernels are ignored.  Every call on
+ * one device shares that device's scratch, which keeps the last call's
+ * contents (nothing in it must start at zero); calls that overlap on one GPU
+ * (from other threads or streams) race, and the caller must serialise them. */
+#define FTGCR_NOALLOC_SCRATCH_BYTES (64u << 20)
+ftgcr_status ftgcr_solve_noalloc(ftgcr_handle* h, const double* rhs_dev, double* x_dev, double tol, int32_t k,
+                                 const ftgcr_fault_plan* plan, ftgcr_stats* stats);
+
 /* Solve n independent problems at once (an ensemble): every handle must be
  * FP64, have its own workspace and share the first handle's stream; their
  * step kernels run as combined launches over all unfinished members, each

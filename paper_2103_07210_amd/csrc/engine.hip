@@ -1019,6 +1019,40 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     return FTGCR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+
+std::mutex g_scratch_mutex;
+std::map<int, void*> g_scratch_ptr;   // device -> address of `scratch` there
+
+}  // namespace
+
+// Working vectors and fault-plan staging of ftgcr_solve_noalloc.  Every GPU
+// the library runs on holds its own copy at its own address until the process
+// ends; in host code `scratch` is only a stand-in for the symbol, never a
+// device address: host code uses the address hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[FTGCR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of `scratch` on device `dev`, which must be current: looked
+// up on the first call on that device, then kept.
+ftgcr_status scratch_on_device(ftgcr_handle* h, int dev, void** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(h, FTGCR_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return FTGCR_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1162,6 +1196,30 @@ ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev, 
     HIP_TRY(h, hipSetDevice(h->device));
     if (h->precision == FTGCR_MIXED) return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
     return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
+}
+
+ftgcr_status ftgcr_solve_noalloc(ftgcr_handle* h, const double* rhs_dev, double* x_dev, double tol, int32_t k,
+                                 const ftgcr_fault_plan* plan, ftgcr_stats* stats)
+{
+    if (!h) return FTGCR_E_INVALID;
+    if (!rhs_dev || !x_dev) return fail(h, FTGCR_E_INVALID, "rhs or x is NULL");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(h, FTGCR_E_INVALID, "tol must be finite and > 0");
+    if (k < 1 || k > h->kmax) return fail(h, FTGCR_E_INVALID, "k must be in [1, kmax]");
+    const size_t need = align256(layout(h).total);
+    if (need > (size_t)FTGCR_NOALLOC_SCRATCH_BYTES)
+        return fail(h, FTGCR_E_WORKSPACE, "the allocation-free solve needs " + std::to_string(need) +
+                                              " bytes of scratch for this grid and kmax; it has " +
+                                              std::to_string((size_t)FTGCR_NOALLOC_SCRATCH_BYTES));
+    HIP_TRY(h, hipSetDevice(h->device));
+    void* base = nullptr;
+    ftgcr_status rc = scratch_on_device(h, h->device, &base);
+    if (rc != FTGCR_OK) return rc;
+    // the fault plan's entry lists follow the working vectors
+    char* staging = (char*)base + need;
+    const size_t staging_bytes = (size_t)FTGCR_NOALLOC_SCRATCH_BYTES - need;
+    if (h->precision == FTGCR_MIXED)
+        return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, base, staging, staging_bytes);
+    return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats, base, staging, staging_bytes);
 }
 
 ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double* const* rhs, double* const* x,

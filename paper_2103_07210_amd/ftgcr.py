@@ -23,12 +23,13 @@ PRECOND_NONE, PRECOND_COLUMN = 0, 1
 CONVERGED, MAX_STEPS, STAGNATED, BREAKDOWN = 0, 1, 2, 3
 KMAX = 16
 LOG_CAP = 256
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["ftgcr_default_options", "ftgcr_create", "ftgcr_set_options", "ftgcr_get_options",
             "ftgcr_set_stream", "ftgcr_workspace_bytes", "ftgcr_set_workspace", "ftgcr_solve",
             "ftgcr_solve_batch", "ftgcr_destroy", "ftgcr_last_error", "ftgcr_debug_apply_A",
             "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times", "ftgcr_autotune",
-            "ftgcr_autotune_batch", "ftgcr_bw_probe"]
+            "ftgcr_autotune_batch", "ftgcr_bw_probe", "ftgcr_solve_noalloc"]
 
 
 class FtgcrError(RuntimeError):
@@ -120,6 +121,8 @@ def load():
     lib.ftgcr_solve.argtypes = [H, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(FaultPlan),
                                 ctypes.POINTER(Stats)]
     lib.ftgcr_solve.restype = ctypes.c_int
+    lib.ftgcr_solve_noalloc.argtypes = lib.ftgcr_solve.argtypes
+    lib.ftgcr_solve_noalloc.restype = ctypes.c_int
     lib.ftgcr_solve_batch.argtypes = [ctypes.POINTER(H), ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.POINTER(FaultPlan),
                                       ctypes.POINTER(Stats)]
@@ -263,13 +266,15 @@ class Solver:
         return t.view(self.problem.shape)
 
     def solve(self, rhs, x=None, tol: float = 1e-10, k: int = 3, plan=None,
-              log_cap: int = LOG_CAP, hist_cap: int = 0):
+              log_cap: int = LOG_CAP, hist_cap: int = 0, noalloc: bool = False):
         """Solve A x = rhs; returns (x tensor, stats dict).  x (if given) is
         the initial guess and is overwritten in place when it is already a
-        contiguous FP64 device tensor."""
+        contiguous FP64 device tensor.  noalloc=True calls the
+        allocation-free entry point (ftgcr_solve_noalloc: the library's
+        device scratch instead of the workspace)."""
         import torch
         lib = load()
-        entry = lib.ftgcr_solve
+        entry = lib.ftgcr_solve_noalloc if noalloc else lib.ftgcr_solve
         rhs_t = self._dev(rhs)
         if x is None:
             x_t = torch.zeros_like(rhs_t)
