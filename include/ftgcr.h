@@ -99,7 +99,25 @@ typedef struct {
                                 the combined launches (1, 2, 4, 8 or 16; 0 =
                                 the largest member's own tiling); set by
                                 ftgcr_autotune_batch                            */
+    int32_t method;          /* Krylov method of ftgcr_solve: FTGCR_METHOD_GCR
+                                (FT-GCR(k), Algorithm 1) or FTGCR_METHOD_GMRES
+                                (the same fault layer on restarted GMRES(k);
+                                FP64 handles, single solves)                    */
 } ftgcr_options;
+
+/* options.method.  FTGCR_METHOD_GMRES: right-preconditioned restarted
+ * GMRES(k) with classical Gram-Schmidt and Givens rotations, wrapped in the
+ * fault layer of Algorithm 1 as the paper proposes for other Krylov solvers
+ * (abstract; Section 1): the residual norm must strictly decrease after every
+ * step (the least-squares residual |g_{j+1}| of the cycle) and at the end of
+ * every cycle (the explicit |R - A x|); otherwise x is restored from the
+ * backup taken after the last cycle that passed, and the cycle is redone.
+ * Stats as for GCR; a cycle-end detection is logged with nu = -1, and the
+ * residual history holds |g_{j+1}|^2 per step.  Fault events: X flips x at
+ * the start of the step, R the Arnoldi vector v_j (before P^{-1} reads it),
+ * P and E the preconditioned z_j = P^{-1} v_j, AP w = A z_j before the inner
+ * products. */
+enum { FTGCR_METHOD_GCR = 0, FTGCR_METHOD_GMRES = 1 };
 
 /* Fault injection (test harness).  XOR bit `bit` (or bits[t] per entry) into
  * the IEEE-754 pattern of entries of one working vector (binary64 in FP64

@@ -86,6 +86,12 @@ struct ftgcr_handle {
     double kt_ms[3] = {0, 0, 0};
     long long kt_n[3] = {0, 0, 0};
 
+    // FT-GMRES(k) control state (device), its instance record and a pinned
+    // host copy, allocated with the handle
+    GmState* gm_st = nullptr;
+    GmInst* gm_inst = nullptr;
+    GmState* gm_host = nullptr;
+
     // batched solves led by this handle: device tables kept between calls
     // (grown, never per call) and the captured step chunk of the last
     // launch table shape
@@ -746,6 +752,168 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
 }
 
 // ---------------------------------------------------------------------------
+// FT-GMRES(k) solve
+// ---------------------------------------------------------------------------
+
+// The GMRES working vectors inside the FP64 workspace layout: v_0..v_kmax in
+// the direction slots, z_0..z_{kmax-1} and w in the image slots.
+GmInst make_gm_inst(const ftgcr_handle* h, const double* rhs, double* x, void* ws)
+{
+    const Inst<double> in = make_inst<double>(h, rhs, x, ws);
+    GmInst gi;
+    std::memset(&gi, 0, sizeof gi);
+    gi.g = in.g;
+    for (int l = 0; l <= h->kmax; ++l) gi.U[l] = in.P[l];
+    for (int l = 0; l < h->kmax; ++l) gi.Z[l] = in.AP[l];
+    gi.W = in.AP[h->kmax];
+    gi.X[0] = in.X[0];
+    gi.X[1] = in.X[1];
+    gi.rhs = rhs;
+    gi.st = h->gm_st;
+    gi.part = in.part;
+    gi.pstride = in.pstride;
+    gi.hist = in.hist;
+    gi.hist_cap = in.hist_cap;
+    gi.nblk_st = h->nblk_st;
+    gi.kc = h->kc;
+    gi.tx = h->tx;
+    gi.ty = h->ty;
+    gi.tz = h->tz;
+    return gi;
+}
+
+ftgcr_status gm_solve_impl(ftgcr_handle* h, const double* rhs, double* x, double tol, int k,
+                           const ftgcr_fault_plan* plan, ftgcr_stats* stats, void* ws, void* staging = nullptr,
+                           size_t staging_bytes = 0)
+{
+    using G = GmLaunch;
+    hipStream_t s = h->stream;
+    std::vector<DevEvent> evs;
+    ftgcr_status rc = stage_events(h, plan, evs, staging, staging_bytes);
+    if (rc != FTGCR_OK) return rc;
+    const GmInst gi = make_gm_inst(h, rhs, x, ws);
+    HIP_TRY(h, hipMemcpyAsync(h->gm_inst, &gi, sizeof gi, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    const GmInst* d = h->gm_inst;
+    // geometry and the column grid of the two-lane FP64 column kernel
+    const Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
+    const int nblk_col = (h->geo.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK;
+    const int nst = h->nblk_st, kc = h->kc;
+    GmState* hs = h->gm_host;
+    auto read_head = [&]() -> ftgcr_status {
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(hs, h->gm_st, offsetof(GmState, den), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        return FTGCR_OK;
+    };
+    auto inject = [&](const DevEvent& ev, long long t) {
+        G::event_prep(d, ev.vec, t, s);
+        if (ev.vec == FTGCR_V_X || ev.vec == FTGCR_V_R) G::event_copy(d, nst, kc, s);
+        const int grid = (int)std::max<long long>(1, std::min<long long>((ev.count + 255) / 256, 8192));
+        G::event_inject(d, grid, ev.idx, ev.bits, ev.count, ev.start, ev.bit, s);
+    };
+    // one Arnoldi step; `at` are the fault events of executed step t
+    auto step = [&](const std::vector<const DevEvent*>& at, long long t) {
+        for (const DevEvent* ev : at)
+            if (ev->vec == FTGCR_V_X || ev->vec == FTGCR_V_R) inject(*ev, t);
+        G::precond(tb, d, nblk_col, h->H, s);
+        bool ap = false;
+        for (const DevEvent* ev : at) {
+            if (ev->vec == FTGCR_V_P || ev->vec == FTGCR_V_E) inject(*ev, t);
+            ap = ap || ev->vec == FTGCR_V_AP;
+        }
+        if (ap) {
+            G::stencil(d, nst, kc, 0, s);
+            for (const DevEvent* ev : at)
+                if (ev->vec == FTGCR_V_AP) inject(*ev, t);
+            G::dots(d, nst, kc, s);
+        } else {
+            G::stencil(d, nst, kc, 1, s);
+        }
+        G::finish_h(d, s);
+        G::orth(d, nst, kc, s);
+        G::finish_step(d, s);
+    };
+    HIP_TRY(h, hipEventRecord(h->ev_start, s));
+    G::init(d, k, h->opt.ft, h->opt.max_steps, tol * tol, s);
+    size_t evp = 0;
+    const std::vector<const DevEvent*> none;
+    const long long guard = 4 * (h->opt.max_steps + 16) + 64;
+    for (long long iter = 0;; ++iter) {
+        if (iter > guard) return fail(h, FTGCR_E_HIP, "GMRES cycle loop did not terminate");
+        G::residual(d, nst, kc, s);
+        G::restart(d, s);
+        rc = read_head();
+        if (rc != FTGCR_OK) return rc;
+        if (hs->status != RUNNING) break;
+        if (!hs->active) continue;   // rolled back at the cycle's end: the restored x's residual next
+        while (evp < evs.size() && evs[evp].step <= hs->s) ++evp;
+        if (evp < evs.size() && evs[evp].step <= hs->s + k) {
+            // a fault event falls in this cycle: step by step, reading the
+            // executed-step count before each step
+            for (int j = 0; j < k; ++j) {
+                if (j > 0) {
+                    rc = read_head();
+                    if (rc != FTGCR_OK) return rc;
+                    if (hs->status != RUNNING || !hs->active) break;
+                }
+                const long long t = hs->s + 1;
+                while (evp < evs.size() && evs[evp].step < t) ++evp;
+                std::vector<const DevEvent*> at;
+                for (size_t q = evp; q < evs.size() && evs[q].step == t; ++q) at.push_back(&evs[q]);
+                step(at, t);
+            }
+        } else {
+            for (int j = 0; j < k; ++j) step(none, 0);
+        }
+        G::xupd(d, nst, kc, s);
+        G::finish_x(d, s);
+    }
+    G::finalize(d, nst, kc, s);
+    HIP_TRY(h, hipEventRecord(h->ev_stop, s));
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(hs, h->gm_st, sizeof(GmState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    if (stats) {
+        stats->status = hs->status;
+        stats->detections = hs->detections;
+        stats->stagnation_accepts = hs->stagnation_accepts;
+        stats->events_applied = hs->events_applied;
+        stats->steps_executed = hs->s;
+        stats->steps_accepted = hs->accepted;
+        stats->steps_wasted = hs->s - hs->accepted;
+        stats->cycles = hs->cycles;
+        stats->refinements = 0;
+        stats->rhs_norm2 = hs->RR;
+        stats->rr_final = hs->rho2;
+        stats->rel_res_recursive = hs->RR > 0 ? std::sqrt(hs->rho2 / hs->RR) : 0.0;
+        stats->rel_res_true = stats->rel_res_recursive;
+        stats->time_ms = ms;
+        stats->log_len = 0;
+        if (stats->log && stats->log_cap > 0) {
+            const int nlog = std::min(std::min(hs->log_len, LOG_CAP), stats->log_cap);
+            for (int q = 0; q < nlog; ++q) {
+                stats->log[q].step = hs->log[q].step;
+                stats->log[q].nu = hs->log[q].nu;
+                stats->log[q].action = hs->log[q].action;
+                stats->log[q].rr_old = hs->log[q].rr_old;
+                stats->log[q].rr_new = hs->log[q].rr_new;
+            }
+            stats->log_len = nlog;
+        }
+        stats->hist_len = 0;
+        if (stats->hist && stats->hist_cap > 0) {
+            const long long nh = std::min<long long>(std::min<long long>(hs->s, h->opt.hist_cap), stats->hist_cap);
+            if (nh > 0) HIP_TRY(h, hipMemcpy(stats->hist, gi.hist, (size_t)nh * sizeof(double), hipMemcpyDeviceToHost));
+            stats->hist_len = nh;
+        }
+    }
+    return FTGCR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // batched solve
 // ---------------------------------------------------------------------------
 //
@@ -1123,6 +1291,8 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
         hipMalloc(&h->inst_dbg, sizeof(Inst<double>)) != hipSuccess ||
         hipMalloc(&h->blk0, 6 * sizeof(int)) != hipSuccess ||
         hipHostMalloc(&h->st_host, sizeof(SolveState)) != hipSuccess ||
+        hipMalloc(&h->gm_st, sizeof(GmState)) != hipSuccess || hipMalloc(&h->gm_inst, sizeof(GmInst)) != hipSuccess ||
+        hipHostMalloc(&h->gm_host, sizeof(GmState)) != hipSuccess ||
         hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_stop) != hipSuccess) {
         h->err = "device allocation failed";
         return bail(FTGCR_E_NOMEM);
@@ -1141,8 +1311,11 @@ ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt)
 {
     if (!h || !opt) return FTGCR_E_INVALID;
     if (opt->poll_steps < 1 || opt->max_steps < 0 || opt->hist_cap < 0 || opt->max_refinements < 0 ||
-        opt->inner_max_steps < 1 || !(opt->inner_tol > 0) || !(opt->inner_tol < 1))
+        opt->inner_max_steps < 1 || !(opt->inner_tol > 0) || !(opt->inner_tol < 1) ||
+        (opt->method != FTGCR_METHOD_GCR && opt->method != FTGCR_METHOD_GMRES))
         return fail(h, FTGCR_E_INVALID, "invalid options");
+    if (opt->method == FTGCR_METHOD_GMRES && h->precision != FTGCR_FP64)
+        return fail(h, FTGCR_E_UNSUPPORTED, "FT-GMRES is built for FP64 handles");
     h->opt = *opt;
     set_tiling(h);
     if (h->graph) {
@@ -1194,6 +1367,7 @@ ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev, 
     if (!h->ws) return fail(h, FTGCR_E_WORKSPACE, "no workspace set");
     if (h->ws_bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "workspace smaller than required by the current options");
     HIP_TRY(h, hipSetDevice(h->device));
+    if (h->opt.method == FTGCR_METHOD_GMRES) return gm_solve_impl(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
     if (h->precision == FTGCR_MIXED) return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
     return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
 }
@@ -1217,6 +1391,8 @@ ftgcr_status ftgcr_solve_noalloc(ftgcr_handle* h, const double* rhs_dev, double*
     // the fault plan's entry lists follow the working vectors
     char* staging = (char*)base + need;
     const size_t staging_bytes = (size_t)FTGCR_NOALLOC_SCRATCH_BYTES - need;
+    if (h->opt.method == FTGCR_METHOD_GMRES)
+        return gm_solve_impl(h, rhs_dev, x_dev, tol, k, plan, stats, base, staging, staging_bytes);
     if (h->precision == FTGCR_MIXED)
         return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, base, staging, staging_bytes);
     return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats, base, staging, staging_bytes);
@@ -1230,6 +1406,8 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
         ftgcr_handle* h = hs[m];
         if (!h) return FTGCR_E_INVALID;
         if (h->precision != FTGCR_FP64) return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are FP64 only");
+        if (h->opt.method != FTGCR_METHOD_GCR)
+            return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves run FT-GCR (options.method of every member)");
         if (!rhs[m] || !x[m]) return fail(hs[0], FTGCR_E_INVALID, "rhs or x is NULL");
         if (!(tol[m] > 0) || !std::isfinite(tol[m])) return fail(hs[0], FTGCR_E_INVALID, "tol must be finite and > 0");
         if (k < 1 || k > h->kmax) return fail(hs[0], FTGCR_E_INVALID, "k must be in [1, kmax] of every member");
@@ -1402,6 +1580,9 @@ void ftgcr_destroy(ftgcr_handle* h)
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
     if (h->ev_idx) (void)hipFree(h->ev_idx);
     if (h->ev_bits) (void)hipFree(h->ev_bits);
+    if (h->gm_st) (void)hipFree(h->gm_st);
+    if (h->gm_inst) (void)hipFree(h->gm_inst);
+    if (h->gm_host) (void)hipHostFree(h->gm_host);
     if (h->batch.graph) (void)hipGraphExecDestroy(h->batch.graph);
     (void)hipFree(h->batch.inst);
     (void)hipFree(h->batch.blk0);

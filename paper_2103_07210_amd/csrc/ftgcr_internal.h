@@ -135,6 +135,49 @@ struct Inst {
     int nblk_dir, kc_dir, tz_dir;
 };
 
+// FT-GMRES(k) control state of one solve (device memory; written by single
+// threads of the one-block kernels, and by the event preparation kernel).
+struct GmState {
+    int status;          // RUNNING or an FTGCR_* outcome
+    int active;          // 1: the cycle's steps run
+    int j;               // step index inside the cycle
+    int k, ft;
+    int phase;           // next restart pass: GM_INIT, GM_CHECK (a cycle ended), GM_REDO (after a rollback)
+    int jdone;           // steps of this cycle that count
+    int cycle_end;       // 1: the cycle is complete, its correction is pending
+    int capped;          // 1: the step cap cut the cycle
+    int x_cur, x_bak, x_dst;
+    int detections, stagnation_accepts, events_applied, events_since_rb;
+    int log_len;
+    int ev_ok, ev_vec, ev_copy, ev_src, ev_dst;
+    long long s, max_steps, accepted, cycles, last_rb_pos, b_accepted;
+    double tol2, T, RR;
+    double rho2;         // explicit |R - A x|^2 of the cycle's start (or of the last check)
+    double b_rho2;       // the backup's
+    double rr_old;       // |g_j|^2 of the previous step (the detector's reference)
+    double den[KMAX + 1];            // stored U[i] = den[i] * v_i (1 once stored normalised)
+    double H[(KMAX + 1) * KMAX];     // Hessenberg, row-major with row stride KMAX, rotated in place
+    double cs[KMAX], sn[KMAX];       // Givens rotations
+    double g[KMAX + 1];              // rotated right-hand side, g_0 = |s|
+    DetectRec log[LOG_CAP];
+};
+
+// Everything the FT-GMRES kernels of one solve need (device copy per solve).
+struct GmInst {
+    Geo g;
+    double* U[KMAX + 1];     // Arnoldi vectors v_i (v_0 = s / |s|), stored scaled by den[i] until normalised
+    double* Z[KMAX];         // z_i = P^{-1} v_i
+    double* W;               // A z_j, then the orthogonalised vector
+    double* X[2];            // X[0]: caller's x, X[1]: workspace
+    const double* rhs;
+    GmState* st;
+    double* part;
+    long long pstride;
+    double* hist;
+    long long hist_cap;
+    int nblk_st, kc, tx, ty, tz;
+};
+
 // Launch table for combined (batched) launches: block b of a launch belongs
 // to instance inst_of(b); blk0[m] is the first block of instance m.
 template <typename T>
@@ -177,6 +220,29 @@ template <typename T> struct Launch {
     // parity entry points (FP64 only)
     static void debug_apply_A(const Table<T>& tb, int total_st_blocks, int kc, const double* in, double* out, hipStream_t s);
     static void debug_pinv(const Table<T>& tb, int total_col_blocks, int H, const double* in, double* out, hipStream_t s);
+};
+
+// FT-GMRES(k) launchers (kernels.hip); gi is the device copy of the solve's
+// GmInst, `tb` the handle's single-instance table (geometry and column grid)
+// for the column pass.
+struct GmLaunch {
+    static void init(const GmInst* gi, int k, int ft, long long max_steps, double tol2, hipStream_t s);
+    static void residual(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void restart(const GmInst* gi, hipStream_t s);
+    static void precond(const Table<double>& tb, const GmInst* gi, int nblk_col, int H, hipStream_t s);
+    // dots = 0: store A z_j only (the dots follow a fault event on it)
+    static void stencil(const GmInst* gi, int nblk_st, int kc, int dots, hipStream_t s);
+    static void dots(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void finish_h(const GmInst* gi, hipStream_t s);
+    static void orth(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void finish_step(const GmInst* gi, hipStream_t s);
+    static void xupd(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void finish_x(const GmInst* gi, hipStream_t s);
+    static void finalize(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void event_prep(const GmInst* gi, int vec, long long step, hipStream_t s);
+    static void event_copy(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void event_inject(const GmInst* gi, int grid, const long long* idx, const unsigned char* bits,
+                             long long count, long long start, int bit, hipStream_t s);
 };
 
 // Plain streaming copy of `bytes` (a multiple of 16, 16-byte aligned

@@ -38,7 +38,8 @@
 
 namespace ftgcr {
 
-enum { MODE_STEP = 0, MODE_INIT = 1, MODE_DEBUG = 2 };
+enum { MODE_STEP = 0, MODE_INIT = 1, MODE_DEBUG = 2, MODE_GM = 3 };
+enum { GM_INIT = 0, GM_CHECK = 1, GM_REDO = 2 };
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -133,8 +134,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 // order of the additions is the same for every (G, U).  The returned LDS
 // array holds the nv sums; out, if not null, gets the first two of them in
 // registers.  Both are valid in every thread.
-template <int G, int U, typename T>
-__device__ __forceinline__ const double* sum_partials(const Inst<T>& in, int nblk, int row0, int nv, double* out)
+template <int G, int U, typename I>
+__device__ __forceinline__ const double* sum_partials(const I& in, int nblk, int row0, int nv, double* out)
 {
     constexpr int NW = RED_THREADS / 64;
     __shared__ double sh[NV_MAX][NW];
@@ -848,8 +849,12 @@ __device__ void decide_beta(SolveState* st, double num, double dn, int init)
 // issued before its first store (r is updated in place after the first pass
 // of a cycle, so program order must not interleave them).
 
+// MODE_GM (FT-GMRES, FP64): the current Arnoldi vector U[j] is divided by
+// den[j] (normalised, written back in place) and z_j = P^{-1} v_j goes to
+// Z[j]; no norms.
 template <typename T, int H, int mode>
-__global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, const T* dbg_in, T* dbg_out)
+__global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, const T* dbg_in, T* dbg_out,
+                                                                const GmInst* gm)
 {
     // The column solve runs in the storage precision: FP64 for FP64 solves;
     // binary32 for the mixed form, where e = P^{-1} r only has to be a fixed
@@ -863,9 +868,12 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_col[m];
     SolveState* st = in.st;
-    if (mode != MODE_DEBUG) {
+    if (mode == MODE_STEP || mode == MODE_INIT) {
         if (st->status != RUNNING) return;
         if (mode == MODE_STEP && st->d_cur == 0.0) return;   // the decision records the breakdown
+    }
+    if (mode == MODE_GM) {
+        if (gm->st->status != RUNNING || !gm->st->active) return;
     }
     // everything read from the instance and the state is copied to registers
     // before the first store, so no later access can wait behind a store
@@ -881,11 +889,19 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     T* rout;
     T* eout;
     double beta = 0.0;
+    double den = 1.0;
     if (mode == MODE_DEBUG) {
         rin = dbg_in;
         ap = dbg_in;
         rout = nullptr;
         eout = dbg_out;
+    } else if (mode == MODE_GM) {
+        const int jj = gm->st->j;
+        rin = (const T*)gm->U[jj];
+        ap = rin;
+        rout = (T*)gm->U[jj];
+        eout = (T*)gm->Z[jj];
+        den = gm->st->den[jj];
     } else {
         rin = in.R[st->r_cur];
         eout = in.E;
@@ -948,7 +964,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     // r+ is stored through a pointer that walks one level per row (a fresh
     // induction value, so the loads' 64-bit addresses need not stay live)
     const long long wstep = upper ? -plane : plane;
-    gptr_mut<T> rw = as_global_mut(mode == MODE_STEP ? rout : eout) + (long long)colc + plane * (upper ? nz - 1 : 0);
+    gptr_mut<T> rw = as_global_mut((mode == MODE_STEP || mode == MODE_GM) ? rout : eout) + (long long)colc +
+                     plane * (upper ? nz - 1 : 0);
     asm volatile("" : "+v"(rw));
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
@@ -983,12 +1000,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
             int k = upper ? nz - 1 - q : q;
             k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
             const double v = (mode == MODE_STEP) ? fma(beta, (double)bufa[b][t], (double)bufr[b][t])
+                             : (mode == MODE_GM) ? (double)bufr[b][t] / den
                                                  : (double)bufr[b][t];
             const T sv = (T)v;
             const double rp = (double)sv;
             const CT rc = (CT)sv;
             if (mine && valid) {
-                if (mode == MODE_STEP) *rw = sv;
+                if (mode == MODE_STEP || mode == MODE_GM) *rw = sv;
                 acc_new = fma(v, v, acc_new);
                 acc_st = fma(rp, rp, acc_st);
             }
@@ -1053,7 +1071,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
             ep += estep;
         }
     }
-    if (mode == MODE_DEBUG) return;
+    if (mode == MODE_DEBUG || mode == MODE_GM) return;
     const double sn = block_sum(acc_new, sh);
     const double ss = block_sum(acc_st, sh);
     if (threadIdx.x == 0) {
@@ -1787,10 +1805,11 @@ void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hi
     }
     if (mode == MODE_STEP)
         FTGCR_H_SWITCH(H, FTGCR_TIMED_LAUNCH(e0, e1, (k_update_thomas<T, HV, MODE_STEP>), dim3(total),
-                                             dim3(COL_THREADS), s, tb, (const T*)nullptr, (T*)nullptr))
+                                             dim3(COL_THREADS), s, tb, (const T*)nullptr, (T*)nullptr,
+                                             (const GmInst*)nullptr))
     else
         FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV, MODE_INIT>), dim3(total), dim3(COL_THREADS), 0,
-                                             s, tb, (const T*)nullptr, (T*)nullptr))
+                                             s, tb, (const T*)nullptr, (T*)nullptr, (const GmInst*)nullptr))
 }
 
 template <typename T>
@@ -1891,7 +1910,7 @@ void Launch<double>::debug_pinv(const Table<double>& tb, int total, int H, const
                                 hipStream_t s)
 {
     FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_DEBUG>), dim3(total), dim3(COL_THREADS),
-                                         0, s, tb, in, out));
+                                         0, s, tb, in, out, (const GmInst*)nullptr));
 }
 
 // Status and step count of every instance into a small device array (one
@@ -1914,6 +1933,598 @@ void Launch<T>::gather_status(const Table<T>& tb, long long* out, hipStream_t s)
 
 template struct Launch<double>;
 template struct Launch<float>;
+
+// ---------------------------------------------------------------------------
+// FT-GMRES(k): the fault layer of Algorithm 1 on restarted GMRES(k)
+// ---------------------------------------------------------------------------
+//
+// Right-preconditioned restarted GMRES with classical Gram-Schmidt and Givens
+// rotations; the residual-norm test after every step (on the rotated
+// right-hand side |g_{j+1}|, the minimised residual norm of the cycle) and on
+// the explicit residual at the end of every cycle, the backup [x, |s|^2] of
+// each cycle that passes, the rollback and the stagnation rule of FT-GCR.
+// Per cycle the host enqueues: residual s = R - A x (into U[0]), restart (the
+// cycle-end decisions, then g_0 = |s|); k steps of
+//   precond      v_j = U[j] / den[j] (written back), z_j = P^{-1} v_j
+//   stencil      w = A z_j (stored) and the partials of <w, v_i>, i <= j
+//   finish_h     h_ij
+//   orth         w - sum_i h_ij v_i into U[j+1], partials of its norm
+//   finish_step  h_{j+1,j}, rotations, |g_{j+1}|^2, exit and fault tests
+// then xupd (x + sum_i y_i z_i, y from the triangular system) and finish_x.
+// Every step kernel returns at once once the cycle is inactive (ended,
+// rolled back or the solve finished), so a cycle is a fixed launch sequence.
+
+__device__ __forceinline__ StPos gm_pos(const GmInst& in, int lb)
+{
+    StPos p;
+    const int bx = lb % in.tx;
+    const int t = lb / in.tx;
+    const int by = t % in.ty;
+    const int bz = t / in.ty;
+    const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
+    const int j = by * ST_TY + (threadIdx.x / ST_TX);
+    p.col_ok = i < in.g.nx && j < in.g.ny;
+    p.i = i < in.g.nx ? i : in.g.nx - 1;
+    p.j = j < in.g.ny ? j : in.g.ny - 1;
+    p.k0 = bz * in.kc;
+    return p;
+}
+
+__global__ void k_gm_init(const GmInst* gi, int k, int ft, long long max_steps, double tol2)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    GmState* st = gi->st;
+    st->status = RUNNING;
+    st->active = 0;
+    st->j = 0;
+    st->k = k;
+    st->ft = ft;
+    st->phase = GM_INIT;
+    st->jdone = 0;
+    st->cycle_end = 0;
+    st->capped = 0;
+    st->x_cur = 0;
+    st->x_bak = 0;
+    st->x_dst = 0;
+    st->detections = 0;
+    st->stagnation_accepts = 0;
+    st->events_applied = 0;
+    st->events_since_rb = 1;
+    st->log_len = 0;
+    st->ev_ok = 0;
+    st->s = 0;
+    st->max_steps = max_steps;
+    st->accepted = 0;
+    st->cycles = 0;
+    st->last_rb_pos = -1;
+    st->b_accepted = 0;
+    st->tol2 = tol2;
+}
+
+// s = R - A x into U[0]; partials of <R, R> (row 0) and <s, s> (row 1).
+template <int KC>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_residual(const GmInst* gi)
+{
+    __shared__ double sh[4];
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (st->status != RUNNING) return;
+    const StPos ps = gm_pos(in, blockIdx.x);
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    double ax[KC], b[KC];
+    stencil_chunk<double, KC>(in.g, in.X[st->x_cur], ps.i, ps.j, ps.k0, ax);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        b[kk] = in.rhs[c0 + plane * kq];
+    }
+    double ss = 0.0, bb = 0.0;
+    double* u0 = in.U[0];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        const double r = ok ? b[kk] - ax[kk] : 0.0;
+        const double bv = ok ? b[kk] : 0.0;
+        if (ok) u0[c0 + plane * (ps.k0 + kk)] = r;
+        ss = fma(r, r, ss);
+        bb = fma(bv, bv, bb);
+    }
+    const double sb = block_sum(bb, sh);
+    const double sr = block_sum(ss, sh);
+    if (threadIdx.x == 0) {
+        in.part[blockIdx.x] = sb;
+        in.part[in.pstride + blockIdx.x] = sr;
+    }
+}
+
+__device__ void gm_log(GmState* st, long long step, int nu, int action, double rr_old, double rr_new)
+{
+    st->detections += 1;
+    if (st->log_len < LOG_CAP) {
+        DetectRec& rec = st->log[st->log_len++];
+        rec.step = step;
+        rec.nu = nu;
+        rec.action = action;
+        rec.rr_old = rr_old;
+        rec.rr_new = rr_new;
+    }
+}
+
+// The explicit residual's decisions (first pass: the initial state; after
+// a cycle: exit test, then the fault test against the backup, then the new
+// backup; after a rollback: none), then a new cycle from |s|.
+__global__ __launch_bounds__(RED_THREADS) void k_gm_restart(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    GmState* st = in.st;
+    if (st->status != RUNNING) return;
+    double v[2];
+    sum_partials<2, 8>(in, in.nblk_st, 0, 2, v);
+    if (threadIdx.x != 0) return;
+    const double rho2 = v[1];
+    st->rho2 = rho2;
+    if (st->phase == GM_INIT) {
+        st->RR = v[0];
+        st->T = st->tol2 * v[0];
+        if (rho2 <= st->T) {
+            st->status = FTGCR_CONVERGED;
+            return;
+        }
+        st->x_bak = st->x_cur;
+        st->b_rho2 = rho2;
+        st->b_accepted = 0;
+    } else if (st->phase == GM_CHECK) {
+        if (st->capped || (st->s >= st->max_steps && rho2 > st->T)) {
+            st->status = FTGCR_MAX_STEPS;
+            return;
+        }
+        if (rho2 <= st->T) {
+            st->status = FTGCR_CONVERGED;
+            return;
+        }
+        if (st->ft && !(rho2 < st->b_rho2)) {   // NaN included
+            const long long pos = 2 * st->accepted + 1;
+            const int stag = (pos == st->last_rb_pos) && !st->events_since_rb;
+            gm_log(st, st->s, -1, stag, st->b_rho2, rho2);
+            if (!stag) {
+                st->x_cur = st->x_bak;
+                st->accepted = st->b_accepted;
+                st->last_rb_pos = pos;
+                st->events_since_rb = 0;
+                st->phase = GM_REDO;
+                st->active = 0;
+                st->cycle_end = 0;
+                return;   // the next residual pass is that of the restored x
+            }
+            st->stagnation_accepts += 1;
+        }
+        if (st->ft) {
+            st->x_bak = st->x_cur;
+            st->b_rho2 = rho2;
+            st->b_accepted = st->accepted;
+        }
+    }
+    if (st->s >= st->max_steps) {
+        st->status = FTGCR_MAX_STEPS;
+        return;
+    }
+    const double rho = sqrt(rho2);
+    st->den[0] = rho;
+    st->g[0] = rho;
+    for (int i = 1; i <= st->k; ++i) st->g[i] = 0.0;
+    st->rr_old = rho2;
+    st->j = 0;
+    st->jdone = 0;
+    st->cycle_end = 0;
+    st->capped = 0;
+    st->active = 1;
+    st->phase = GM_CHECK;
+}
+
+// The partials of <w, v_i>, i <= j, of a block's cells (rows DOT_ROW0 + i).
+template <int KC>
+__device__ __forceinline__ void gm_dots(const GmInst& in, const StPos& ps, const double (&w)[KC], int j)
+{
+    __shared__ double sh[KMAX + 1][4];
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = 0; i <= j; ++i) {
+        const double* vi = in.U[i];
+        double acc = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const bool ok = ps.col_ok && ps.k0 + kk < nz;
+            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+            const double vv = vi[c0 + plane * kq];
+            acc = fma(w[kk], ok ? vv : 0.0, acc);
+        }
+        const double t = wave_sum(acc);
+        if (lane == 0) sh[i][wv] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= j) {
+        const int i = threadIdx.x;
+        in.part[(long long)(DOT_ROW0 + i) * in.pstride + blockIdx.x] = ((sh[i][0] + sh[i][1]) + sh[i][2]) + sh[i][3];
+    }
+}
+
+// w = A z_j into W; with DOTS also the partials of <w, v_i>.
+template <int KC, int DOTS>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_stencil(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (st->status != RUNNING || !st->active) return;
+    const int j = st->j;
+    const StPos ps = gm_pos(in, blockIdx.x);
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    double w[KC];
+    stencil_chunk<double, KC>(in.g, in.Z[j], ps.i, ps.j, ps.k0, w);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        if (ok) in.W[c0 + plane * (ps.k0 + kk)] = w[kk];
+        else w[kk] = 0.0;
+    }
+    if (DOTS) gm_dots<KC>(in, ps, w, j);
+}
+
+// The partials of <w, v_i> from the stored w (after a fault event on it).
+template <int KC>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_dots(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (st->status != RUNNING || !st->active) return;
+    const StPos ps = gm_pos(in, blockIdx.x);
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    double w[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        const double v = in.W[c0 + plane * kq];
+        w[kk] = ok ? v : 0.0;
+    }
+    gm_dots<KC>(in, ps, w, st->j);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_gm_finish_h(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    GmState* st = in.st;
+    if (st->status != RUNNING || !st->active) return;
+    const int j = st->j;
+    const double* v = sum_partials<4, 4>(in, in.nblk_st, DOT_ROW0, j + 1, nullptr);
+    if ((int)threadIdx.x <= j) st->H[threadIdx.x * KMAX + j] = v[threadIdx.x];
+}
+
+// U[j+1] = w - sum_i h_ij v_i (ascending i); partials of its squared norm.
+template <int KC>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_orth(const GmInst* gi)
+{
+    __shared__ double sh[4];
+    __shared__ double s_h[KMAX + 1];
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (st->status != RUNNING || !st->active) return;
+    const int j = st->j;
+    if ((int)threadIdx.x <= j) s_h[threadIdx.x] = st->H[threadIdx.x * KMAX + j];
+    __syncthreads();
+    const StPos ps = gm_pos(in, blockIdx.x);
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    double* un = in.U[j + 1];
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        const long long c = c0 + plane * kq;
+        double w = in.W[c];
+        for (int i = 0; i <= j; ++i) w = w - s_h[i] * in.U[i][c];
+        if (ok) un[c] = w;
+        const double wd = ok ? w : 0.0;
+        acc = fma(wd, wd, acc);
+    }
+    const double sw = block_sum(acc, sh);
+    if (threadIdx.x == 0) in.part[blockIdx.x] = sw;
+}
+
+// h_{j+1,j}, the rotations, the step's residual norm |g_{j+1}|^2, then the
+// exit test and the fault test of the step.
+__global__ __launch_bounds__(RED_THREADS) void k_gm_finish_step(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    GmState* st = in.st;
+    if (st->status != RUNNING || !st->active) return;
+    double v[2];
+    sum_partials<2, 8>(in, in.nblk_st, 0, 1, v);
+    if (threadIdx.x != 0) return;
+    const int j = st->j;
+    double* H = st->H;
+    const double hn = sqrt(v[0]);
+    H[(j + 1) * KMAX + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i * KMAX + j], b = H[(i + 1) * KMAX + j];
+        H[i * KMAX + j] = st->cs[i] * a + st->sn[i] * b;
+        H[(i + 1) * KMAX + j] = -st->sn[i] * a + st->cs[i] * b;
+    }
+    {
+        const double a = H[j * KMAX + j], b = H[(j + 1) * KMAX + j];
+        const double den = sqrt(a * a + b * b);
+        st->cs[j] = a / den;
+        st->sn[j] = b / den;
+        H[j * KMAX + j] = den;
+        H[(j + 1) * KMAX + j] = 0.0;
+        st->g[j + 1] = -st->sn[j] * st->g[j];
+        st->g[j] = st->cs[j] * st->g[j];
+    }
+    const double rr_new = st->g[j + 1] * st->g[j + 1];
+    st->s += 1;
+    const long long s = st->s;
+    if (j == 0) st->cycles += 1;
+    if (s <= in.hist_cap) in.hist[s - 1] = rr_new;
+    st->jdone = j + 1;
+    if (rr_new <= st->T) {   // exit test first: the cycle ends, the check follows
+        st->accepted += 1;
+        st->rr_old = rr_new;
+        st->cycle_end = 1;
+        st->active = 0;
+        return;
+    }
+    if (st->ft && !(rr_new < st->rr_old)) {   // NaN included
+        const long long pos = 2 * (st->accepted + 1);
+        const int stag = (pos == st->last_rb_pos) && !st->events_since_rb;
+        gm_log(st, s, j, stag, st->rr_old, rr_new);
+        if (!stag) {
+            st->x_cur = st->x_bak;
+            st->accepted = st->b_accepted;
+            st->last_rb_pos = pos;
+            st->events_since_rb = 0;
+            st->phase = GM_REDO;
+            st->active = 0;
+            st->cycle_end = 0;
+            return;
+        }
+        st->stagnation_accepts += 1;
+    }
+    st->accepted += 1;
+    st->rr_old = rr_new;
+    if (hn == 0.0 || j + 1 == st->k) {   // the cycle is complete (or its space holds the solution)
+        st->cycle_end = 1;
+        st->active = 0;
+        return;
+    }
+    st->den[j + 1] = hn;
+    st->j = j + 1;
+    if (s >= st->max_steps) {   // the next step would pass the cap
+        st->capped = 1;
+        st->cycle_end = 1;
+        st->active = 0;
+    }
+}
+
+// The cycle's correction: y from the rotated triangular system over the
+// steps done, then x + sum_i y_i z_i (ascending i) into a buffer that is not
+// the backup.
+template <int KC>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_xupd(const GmInst* gi)
+{
+    __shared__ double y[KMAX];
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (st->status != RUNNING || !st->cycle_end) return;
+    const int jd = st->jdone;
+    if (threadIdx.x == 0) {
+        const double* H = st->H;
+        for (int i = jd - 1; i >= 0; --i) {
+            double acc = st->g[i];
+            for (int l = i + 1; l < jd; ++l) acc = acc - H[i * KMAX + l] * y[l];
+            y[i] = acc / H[i * KMAX + i];
+        }
+    }
+    __syncthreads();
+    const StPos ps = gm_pos(in, blockIdx.x);
+    if (!ps.col_ok) return;
+    const int nz = in.g.nz;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    const int xs = st->x_cur;
+    const int xd = (st->x_cur == st->x_bak) ? 1 - st->x_cur : st->x_cur;
+    const double* xsrc = in.X[xs];
+    double* xdst = in.X[xd];
+    for (int kk = 0; kk < KC; ++kk) {
+        if (ps.k0 + kk >= nz) break;
+        const long long c = c0 + plane * (ps.k0 + kk);
+        double xv = xsrc[c];
+        for (int i = 0; i < jd; ++i) xv = xv + y[i] * in.Z[i][c];
+        xdst[c] = xv;
+    }
+}
+
+__global__ void k_gm_finish_x(const GmInst* gi)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    GmState* st = gi->st;
+    if (st->status != RUNNING || !st->cycle_end) return;
+    st->x_cur = (st->x_cur == st->x_bak) ? 1 - st->x_cur : st->x_cur;
+}
+
+// The returned iterate into the caller's buffer X[0].
+template <int KC>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_finalize(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (st->x_cur == 0) return;
+    const StPos ps = gm_pos(in, blockIdx.x);
+    if (!ps.col_ok) return;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    for (int kk = 0; kk < KC; ++kk) {
+        if (ps.k0 + kk >= in.g.nz) break;
+        in.X[0][c0 + plane * (ps.k0 + kk)] = in.X[st->x_cur][c0 + plane * (ps.k0 + kk)];
+    }
+}
+
+// Fault events of executed step `step` (they apply only if that step is the
+// one about to run, in an active cycle).  X: x at the start of the step,
+// copied first if it still is the backup's buffer; R: v_j at the start of
+// the step, stored normalised first (the flip acts on v_j itself); P and E:
+// z_j after the preconditioner; AP: w = A z_j before the inner products.
+__global__ void k_gm_event_prep(const GmInst* gi, int vec, long long step)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    GmState* st = gi->st;
+    st->ev_ok = (st->status == RUNNING && st->active && st->s + 1 == step);
+    st->ev_vec = vec;
+    st->ev_copy = 0;
+    if (!st->ev_ok) return;
+    if (vec == FTGCR_V_X && st->x_cur == st->x_bak) {
+        st->ev_copy = 1;
+        st->ev_src = st->x_cur;
+        st->ev_dst = 1 - st->x_cur;
+        st->x_cur = st->ev_dst;
+    } else if (vec == FTGCR_V_R && st->den[st->j] != 1.0) {
+        st->ev_copy = 1;
+    }
+}
+
+template <int KC>
+__global__ __launch_bounds__(ST_THREADS) void k_gm_event_copy(const GmInst* gi)
+{
+    const GmInst& in = *gi;
+    const GmState* st = in.st;
+    if (!st->ev_ok || !st->ev_copy) return;
+    const StPos ps = gm_pos(in, blockIdx.x);
+    if (!ps.col_ok) return;
+    const long long plane = (long long)in.g.ncols;
+    const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
+    const int j = st->j;
+    const double den = st->den[j];
+    for (int kk = 0; kk < KC; ++kk) {
+        if (ps.k0 + kk >= in.g.nz) break;
+        const long long c = c0 + plane * (ps.k0 + kk);
+        if (st->ev_vec == FTGCR_V_X) in.X[st->ev_dst][c] = in.X[st->ev_src][c];
+        else in.U[j][c] = in.U[j][c] / den;
+    }
+}
+
+__global__ void k_gm_event_inject(const GmInst* gi, const long long* idx, const unsigned char* bits, long long count,
+                                  long long start, int bit0)
+{
+    const GmInst& in = *gi;
+    GmState* st = in.st;
+    if (!st->ev_ok) return;
+    const int vec = st->ev_vec;
+    const int j = st->j;
+    double* target = vec == FTGCR_V_X ? in.X[st->x_cur]
+                   : vec == FTGCR_V_R ? in.U[j]
+                   : vec == FTGCR_V_AP ? in.W : in.Z[j];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride) {
+        const long long at = idx ? idx[t] : start + t;
+        const int bit = bits ? (int)bits[t] : bit0;
+        write_xor<double>(target + at, bit);
+    }
+    // the grid's last use of the prepared state is above; the one-thread
+    // bookkeeping below touches fields no thread reads here
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->events_applied += 1;
+        st->events_since_rb = 1;
+        if (vec == FTGCR_V_R) st->den[j] = 1.0;   // v_j is stored normalised now
+    }
+}
+
+void GmLaunch::init(const GmInst* gi, int k, int ft, long long max_steps, double tol2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, gi, k, ft, max_steps, tol2);
+}
+
+void GmLaunch::residual(const GmInst* gi, int nblk, int kc, hipStream_t s)
+{
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_residual<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+}
+
+void GmLaunch::restart(const GmInst* gi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_restart, dim3(1), dim3(RED_THREADS), 0, s, gi);
+}
+
+void GmLaunch::precond(const Table<double>& tb, const GmInst* gi, int nblk_col, int H, hipStream_t s)
+{
+    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_GM>), dim3(nblk_col), dim3(COL_THREADS),
+                                         0, s, tb, (const double*)nullptr, (double*)nullptr, gi));
+}
+
+void GmLaunch::stencil(const GmInst* gi, int nblk, int kc, int dots, hipStream_t s)
+{
+    if (dots)
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_stencil<KCV, 1>), dim3(nblk), dim3(ST_THREADS), 0, s, gi))
+    else
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_stencil<KCV, 0>), dim3(nblk), dim3(ST_THREADS), 0, s, gi))
+}
+
+void GmLaunch::dots(const GmInst* gi, int nblk, int kc, hipStream_t s)
+{
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_dots<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+}
+
+void GmLaunch::finish_h(const GmInst* gi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_finish_h, dim3(1), dim3(RED_THREADS), 0, s, gi);
+}
+
+void GmLaunch::orth(const GmInst* gi, int nblk, int kc, hipStream_t s)
+{
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_orth<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+}
+
+void GmLaunch::finish_step(const GmInst* gi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_finish_step, dim3(1), dim3(RED_THREADS), 0, s, gi);
+}
+
+void GmLaunch::xupd(const GmInst* gi, int nblk, int kc, hipStream_t s)
+{
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_xupd<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+}
+
+void GmLaunch::finish_x(const GmInst* gi, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_finish_x, dim3(1), dim3(64), 0, s, gi);
+}
+
+void GmLaunch::finalize(const GmInst* gi, int nblk, int kc, hipStream_t s)
+{
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_finalize<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+}
+
+void GmLaunch::event_prep(const GmInst* gi, int vec, long long step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_event_prep, dim3(1), dim3(64), 0, s, gi, vec, step);
+}
+
+void GmLaunch::event_copy(const GmInst* gi, int nblk, int kc, hipStream_t s)
+{
+    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_event_copy<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+}
+
+void GmLaunch::event_inject(const GmInst* gi, int grid, const long long* idx, const unsigned char* bits,
+                            long long count, long long start, int bit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gm_event_inject, dim3(grid), dim3(256), 0, s, gi, idx, bits, count, start, bit);
+}
 
 // ---------------------------------------------------------------------------
 // bandwidth probe: a plain streaming copy, the reference for what a kernel

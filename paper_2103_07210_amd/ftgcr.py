@@ -21,6 +21,7 @@ OK, E_INVALID, E_HIP, E_NOMEM, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -
 FP64, MIXED = 0, 1
 PRECOND_NONE, PRECOND_COLUMN = 0, 1
 CONVERGED, MAX_STEPS, STAGNATED, BREAKDOWN = 0, 1, 2, 3
+METHOD_GCR, METHOD_GMRES = 0, 1
 KMAX = 16
 LOG_CAP = 256
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -55,7 +56,7 @@ class Options(ctypes.Structure):
                 ("max_refinements", ctypes.c_int32), ("inner_max_steps", ctypes.c_int32),
                 ("hist_cap", ctypes.c_int64), ("use_graphs", ctypes.c_int32),
                 ("levels_per_block", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
-                ("batch_levels_per_block", ctypes.c_int32)]
+                ("batch_levels_per_block", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
