@@ -225,15 +225,62 @@ int orc_solve(const orc_problem* pb, const double* rhs, double* x, double tol,
                             log, log_cap, hist, hist_cap, NULL, NULL, 0);
 }
 
-int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double tol,
-                     int32_t k, int64_t max_steps, int32_t ft,
-                     const orc_event* events, int32_t n_events, orc_stats* st,
-                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap,
-                     double* cos_r_ap, double* cos_ap, int64_t trace_cap)
+/* The operator pair a solver applies, y = A x and e = P^{-1} r over n
+ * entries, so one rendering of each solver serves every mesh. */
+typedef struct {
+    int64_t n;
+    void (*apply_A)(const void* ctx, const double* x, double* y);
+    void (*apply_pinv)(const void* ctx, const double* r, double* e);
+    const void* ctx;
+} op_pair;
+
+typedef struct {
+    const orc_problem* pb;
+    double* w;   /* face weights wx, wy, wz, one allocation */
+    const double *wx, *wy, *wz;
+} latlon_ctx;
+
+static void latlon_A(const void* c, const double* x, double* y)
 {
-    if (!pb || !rhs || !x || !st || k < 1 || !(tol > 0.0) || max_steps < 0) return -1;
-    if (pb->nx < 3 || pb->ny < 1 || pb->nz < 1) return -1;
+    const latlon_ctx* q = (const latlon_ctx*)c;
+    orc_apply_A(q->pb, q->wx, q->wy, q->wz, x, y);
+}
+
+static void latlon_pinv(const void* c, const double* r, double* e)
+{
+    const latlon_ctx* q = (const latlon_ctx*)c;
+    orc_apply_pinv(q->pb, q->wx, q->wy, q->wz, r, e);
+}
+
+/* Face weights of a lat-lon problem and the operator pair over them. */
+static int latlon_open(const orc_problem* pb, latlon_ctx* q, op_pair* op)
+{
     const int64_t n = (int64_t)pb->nx * pb->ny * pb->nz;
+    const int64_t nwy = (int64_t)pb->nx * (pb->ny + 1) * pb->nz, nwz = (int64_t)pb->nx * pb->ny * (pb->nz + 1);
+    q->pb = pb;
+    q->w = (double*)malloc(sizeof(double) * (size_t)(n + nwy + nwz));
+    if (!q->w) return -1;
+    q->wx = q->w;
+    q->wy = q->w + n;
+    q->wz = q->w + n + nwy;
+    orc_face_weights(pb, q->w, q->w + n, q->w + n + nwy);
+    op->n = n;
+    op->apply_A = latlon_A;
+    op->apply_pinv = latlon_pinv;
+    op->ctx = q;
+    return 0;
+}
+
+static void latlon_close(latlon_ctx* q) { free(q->w); }
+
+static int gcr_core(const op_pair* op, const double* rhs, double* x, double tol,
+                    int32_t k, int64_t max_steps, int32_t ft,
+                    const orc_event* events, int32_t n_events, orc_stats* st,
+                    orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap,
+                    double* cos_r_ap, double* cos_ap, int64_t trace_cap)
+{
+    if (!rhs || !x || !st || k < 1 || !(tol > 0.0) || max_steps < 0) return -1;
+    const int64_t n = op->n;
     for (int32_t q = 0; q < n_events; ++q) {
         const orc_event* ev = &events[q];
         if (ev->vec < ORC_V_X || ev->vec > ORC_V_E || ev->count < 0) return -1;
@@ -245,17 +292,12 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
     }
 
     memset(st, 0, sizeof *st);
-    const int64_t nwx = n, nwy = (int64_t)pb->nx * (pb->ny + 1) * pb->nz,
-                  nwz = (int64_t)pb->nx * pb->ny * (pb->nz + 1);
     /* Working set: x, r, e, L(e), p^0..p^k, L(p^0)..L(p^k), plus the backup
      * [x, r, p^0, L(p^0)]* and the cycle-start copies of x and r. */
     const int nvec = 2 * (k + 1) + 9;
-    double* pool = (double*)malloc(sizeof(double) * (size_t)(nwx + nwy + nwz + nvec * n));
+    double* pool = (double*)malloc(sizeof(double) * (size_t)(nvec * n));
     if (!pool) return -1;
-    double* wx = pool;
-    double* wy = wx + nwx;
-    double* wz = wy + nwy;
-    double* r = wz + nwz;
+    double* r = pool;
     double* e = r + n;
     double* le = e + n;
     double* bx = le + n;   /* backup x   */
@@ -270,17 +312,15 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
     double* alpha = (double*)malloc(sizeof(double) * (size_t)(k + 1));
     if (!d || !alpha) { free(pool); free(d); free(alpha); return -1; }
 
-    orc_face_weights(pb, wx, wy, wz);
-
     /* Initialisation (first line of Algorithm 1): r = L(x) - R, p^0 = P^{-1} r,
      * and L(p^0), which the first beta needs. */
     const double RR = orc_dot(n, rhs, rhs);
     const double T = tol * tol * RR;
     st->rhs_norm2 = RR;
-    orc_apply_A(pb, wx, wy, wz, x, r);
+    op->apply_A(op->ctx, x, r);
     for (int64_t t = 0; t < n; ++t) r[t] = r[t] - rhs[t];
-    orc_apply_pinv(pb, wx, wy, wz, r, pv);
-    orc_apply_A(pb, wx, wy, wz, pv, apv);
+    op->apply_pinv(op->ctx, r, pv);
+    op->apply_A(op->ctx, pv, apv);
     double rr_old = orc_dot(n, r, r);
 
     int status = -1;
@@ -374,14 +414,14 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
             /* S5: e = P^{-1} r, L(e), alpha_l = -<L(e), Lp^l> / <Lp^l, Lp^l>.
              * Planned flips of the preconditioner output (the paper's injection
              * site, Section 3) land on e before anything reads it. */
-            orc_apply_pinv(pb, wx, wy, wz, r, e);
+            op->apply_pinv(op->ctx, r, e);
             for (int32_t q = 0; q < n_events; ++q) {
                 if (events[q].step != s || events[q].vec != ORC_V_E) continue;
                 apply_event(&events[q], e);
                 st->events_applied += 1;
                 events_since_rb = 1;
             }
-            orc_apply_A(pb, wx, wy, wz, e, le);
+            op->apply_A(op->ctx, e, le);
             for (int l = 0; l <= nu; ++l)
                 alpha[l] = -orc_dot(n, le, apv + (int64_t)l * n) / d[l];
 
@@ -423,6 +463,22 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
     return 0;
 }
 
+int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double tol,
+                     int32_t k, int64_t max_steps, int32_t ft,
+                     const orc_event* events, int32_t n_events, orc_stats* st,
+                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap,
+                     double* cos_r_ap, double* cos_ap, int64_t trace_cap)
+{
+    if (!pb || pb->nx < 3 || pb->ny < 1 || pb->nz < 1) return -1;
+    latlon_ctx q;
+    op_pair op;
+    if (latlon_open(pb, &q, &op) != 0) return -1;
+    const int rc = gcr_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist,
+                            hist_cap, cos_r_ap, cos_ap, trace_cap);
+    latlon_close(&q);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------- */
 /* FT-GMRES(k): the same fault-tolerance layer on restarted GMRES.            */
 /* ------------------------------------------------------------------------- */
@@ -461,10 +517,9 @@ int orc_solve_traced(const orc_problem* pb, const double* rhs, double* x, double
  * detection is logged with nu = -1 and the explicit squared norms.
  */
 
-static void residual_RAx(const orc_problem* pb, const double* wx, const double* wy, const double* wz,
-                         const double* rhs, const double* x, double* s, int64_t n)
+static void residual_RAx(const op_pair* op, const double* rhs, const double* x, double* s, int64_t n)
 {
-    orc_apply_A(pb, wx, wy, wz, x, s);
+    op->apply_A(op->ctx, x, s);
     for (int64_t t = 0; t < n; ++t) s[t] = rhs[t] - s[t];
 }
 
@@ -490,14 +545,13 @@ static void apply_events_at(const orc_event* events, int32_t n_events, int64_t s
     }
 }
 
-int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double tol,
-                    int32_t k, int64_t max_steps, int32_t ft,
-                    const orc_event* events, int32_t n_events, orc_stats* st,
-                    orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
+static int gmres_core(const op_pair* op, const double* rhs, double* x, double tol,
+                      int32_t k, int64_t max_steps, int32_t ft,
+                      const orc_event* events, int32_t n_events, orc_stats* st,
+                      orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
 {
-    if (!pb || !rhs || !x || !st || k < 1 || !(tol > 0.0) || max_steps < 0) return -1;
-    if (pb->nx < 3 || pb->ny < 1 || pb->nz < 1) return -1;
-    const int64_t n = (int64_t)pb->nx * pb->ny * pb->nz;
+    if (!rhs || !x || !st || k < 1 || !(tol > 0.0) || max_steps < 0) return -1;
+    const int64_t n = op->n;
     for (int32_t q = 0; q < n_events; ++q) {
         const orc_event* ev = &events[q];
         if (ev->vec < ORC_V_X || ev->vec > ORC_V_E || ev->count < 0) return -1;
@@ -508,11 +562,9 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
         }
     }
     memset(st, 0, sizeof *st);
-    const int64_t nwx = n, nwy = (int64_t)pb->nx * (pb->ny + 1) * pb->nz,
-                  nwz = (int64_t)pb->nx * pb->ny * (pb->nz + 1);
     /* s, w, the backup of x, v_0..v_k, z_0..z_{k-1} */
     const int64_t nvec = 3 + (k + 1) + k;
-    double* pool = (double*)malloc(sizeof(double) * (size_t)(nwx + nwy + nwz + nvec * n));
+    double* pool = (double*)malloc(sizeof(double) * (size_t)(nvec * n));
     double* hh = (double*)calloc((size_t)(k + 1) * k, sizeof(double));   /* H[i][j] = hh[i*k + j] */
     double* cs = (double*)calloc((size_t)k, sizeof(double));
     double* sn = (double*)calloc((size_t)k, sizeof(double));
@@ -522,20 +574,16 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
         free(pool); free(hh); free(cs); free(sn); free(g); free(y);
         return -1;
     }
-    double* wx = pool;
-    double* wy = wx + nwx;
-    double* wz = wy + nwy;
-    double* s = wz + nwz;
+    double* s = pool;
     double* w = s + n;
     double* xb = w + n;
     double* V = xb + n;                  /* v_i = V + i*n, i = 0..k  */
     double* Z = V + (int64_t)(k + 1) * n; /* z_i = Z + i*n, i < k    */
-    orc_face_weights(pb, wx, wy, wz);
 
     const double RR = orc_dot(n, rhs, rhs);
     const double T = tol * tol * RR;
     st->rhs_norm2 = RR;
-    residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+    residual_RAx(op, rhs, x, s, n);
     double rho2 = orc_dot(n, s, s);
     int status = -1;
     if (rho2 <= T) status = ORC_CONVERGED;
@@ -563,9 +611,9 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
             if (j == 0) st->cycles += 1;
             apply_events_at(events, n_events, sx, ORC_V_X, ORC_V_X, x, st, &events_since_rb);
             apply_events_at(events, n_events, sx, ORC_V_R, ORC_V_R, vj, st, &events_since_rb);
-            orc_apply_pinv(pb, wx, wy, wz, vj, zj);
+            op->apply_pinv(op->ctx, vj, zj);
             apply_events_at(events, n_events, sx, ORC_V_P, ORC_V_E, zj, st, &events_since_rb);
-            orc_apply_A(pb, wx, wy, wz, zj, w);
+            op->apply_A(op->ctx, zj, w);
             apply_events_at(events, n_events, sx, ORC_V_AP, ORC_V_AP, w, st, &events_since_rb);
             for (int i = 0; i <= j; ++i) hh[i * k + j] = orc_dot(n, w, V + (int64_t)i * n);
             for (int i = 0; i <= j; ++i) {
@@ -617,7 +665,7 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
             for (int64_t t = 0; t < n; ++t) vn[t] = w[t] / hn;
         }
         if (rolled) {
-            residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+            residual_RAx(op, rhs, x, s, n);
             rho2 = orc_dot(n, s, s);
             continue;
         }
@@ -631,7 +679,7 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
             const double* zi = Z + (int64_t)i * n;
             for (int64_t t = 0; t < n; ++t) x[t] = x[t] + y[i] * zi[t];
         }
-        residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+        residual_RAx(op, rhs, x, s, n);
         const double rho2_new = orc_dot(n, s, s);
         if (capped || (sx >= max_steps && rho2_new > T)) {
             rho2 = rho2_new;
@@ -648,7 +696,7 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
                 accepted = b_accepted;
                 last_rb_pos = pos;
                 events_since_rb = 0;
-                residual_RAx(pb, wx, wy, wz, rhs, x, s, n);
+                residual_RAx(op, rhs, x, s, n);
                 rho2 = orc_dot(n, s, s);
                 continue;
             }
@@ -671,4 +719,416 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
     st->hist_len = sx < hist_cap ? sx : hist_cap;
     free(pool); free(hh); free(cs); free(sn); free(g); free(y);
     return 0;
+}
+
+int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double tol,
+                    int32_t k, int64_t max_steps, int32_t ft,
+                    const orc_event* events, int32_t n_events, orc_stats* st,
+                    orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
+{
+    if (!pb || pb->nx < 3 || pb->ny < 1 || pb->nz < 1) return -1;
+    latlon_ctx q;
+    op_pair op;
+    if (latlon_open(pb, &q, &op) != 0) return -1;
+    const int rc = gmres_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap);
+    latlon_close(&q);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Octahedral reduced Gaussian grid O_N (Section 3, Table 1)                  */
+/* ------------------------------------------------------------------------- */
+/*
+ * 2N latitude rings; the i-th ring from either pole (i = 1..N) holds 4i + 16
+ * points, 4N(N+9) per level (Table 1).  Ring latitudes are the Gaussian
+ * latitudes: their sines are the roots of the Legendre polynomial P_{2N}.
+ * Point m of a ring of n points sits at longitude 2 pi m / n.  Rings are
+ * numbered from the south pole; flat index = (first point of the ring + m)
+ * + points * k.
+ *
+ * Node-centred finite volumes on the triangulated mesh: the points are the
+ * vertices of the polyhedron inscribed in the unit sphere whose triangles
+ * join neighbouring rings ("zipper": walking both rings eastward from
+ * longitude 0, the ring whose next point comes first -- the lower ring on a
+ * tie -- adds a triangle); the polar caps stay open (no flux through the
+ * poles).  A point's control area is its circumcentric (Voronoi) region,
+ * A_a = (1/4) sum_b W_ab |x_a - x_b|^2, and the face between the control
+ * volumes of the ends of an edge (a, b) is orthogonal to it, with length
+ * over edge length W_ab = (cot alpha + cot beta) / 2 (the angles opposite
+ * the edge in its one or two triangles).  Weights, c at the face centre as
+ * on the lat-lon grid (an edge's centre: its chord's midpoint projected
+ * back onto the sphere):
+ *   horizontal   c dz W_ab
+ *   vertical     c A_a / dz between levels, none at bottom and top.
+ * A = A0 + sigma diag(A0) as on the lat-lon grid; P is again the vertical
+ * tridiagonal part of A.
+ */
+
+int64_t orc_oct_cells(int32_t N) { return 4LL * N * (N + 9); }
+
+int32_t orc_oct_ring_points(int32_t N, int32_t j)
+{
+    const int32_t i = j < N ? j + 1 : 2 * N - j;   /* ring index from the nearer pole */
+    return 4 * i + 16;
+}
+
+/* Legendre polynomial P_n(x) and its derivative, by the three-term recurrence. */
+static void legendre(int n, double x, double* p, double* dp)
+{
+    double p0 = 1.0, p1 = x;
+    for (int l = 2; l <= n; ++l) {
+        const double p2 = ((2.0 * l - 1.0) * x * p1 - (l - 1.0) * p0) / l;
+        p0 = p1;
+        p1 = p2;
+    }
+    *p = p1;
+    *dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+void orc_oct_gauss(int32_t N, double* mu, double* w)
+{
+    const int n = 2 * N;
+    for (int l = 0; l < n; ++l) {
+        /* Newton from the usual first guess for the l-th root (descending) */
+        double x = cos(M_PI * (l + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre(n, x, &p, &dp);
+            const double dx = p / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        double p, dp;
+        legendre(n, x, &p, &dp);
+        mu[n - 1 - l] = x;                          /* ascending: south to north */
+        w[n - 1 - l] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+typedef struct {
+    const orc_oct_problem* pb;
+    int32_t nring;
+    int64_t ncell;
+    int32_t* npts;        /* points per ring                              */
+    int64_t* first;       /* first point of each ring                     */
+    double *lon, *lat;    /* per point                                    */
+    double *px, *py, *pz; /* per point, on the unit sphere                */
+    double* area;         /* Voronoi control area per point               */
+    double* hcell;        /* hill height at each point                    */
+    int64_t nedge, cap;
+    int64_t *ea, *eb;     /* edge ends                                    */
+    double* ew;           /* (cot alpha + cot beta) / 2                   */
+    double* eh;           /* hill height at the edge's centre             */
+} oct_mesh;
+
+static double oct_hill(const orc_oct_problem* pb, double lon, double lat)
+{
+    orc_problem q;
+    memset(&q, 0, sizeof q);
+    q.hill_lon = pb->hill_lon;
+    q.hill_lat = pb->hill_lat;
+    q.hill_width = pb->hill_width;
+    return orc_hill(&q, lon, lat);
+}
+
+static void oct_mesh_free(oct_mesh* m)
+{
+    free(m->npts); free(m->first); free(m->lon); free(m->lat); free(m->px); free(m->py); free(m->pz);
+    free(m->area); free(m->hcell); free(m->ea); free(m->eb); free(m->ew); free(m->eh);
+}
+
+/* Index of edge (a, b), added if new (linear search: plain, not fast). */
+static int64_t oct_edge(oct_mesh* m, int64_t a, int64_t b)
+{
+    for (int64_t e = m->nedge - 1; e >= 0 && e >= m->nedge - 64; --e)
+        if ((m->ea[e] == a && m->eb[e] == b) || (m->ea[e] == b && m->eb[e] == a)) return e;
+    for (int64_t e = 0; e < m->nedge; ++e)
+        if ((m->ea[e] == a && m->eb[e] == b) || (m->ea[e] == b && m->eb[e] == a)) return e;
+    if (m->nedge == m->cap) {
+        m->cap = m->cap ? 2 * m->cap : 1024;
+        int64_t* ea = (int64_t*)realloc(m->ea, sizeof(int64_t) * (size_t)m->cap);
+        if (ea) m->ea = ea;
+        int64_t* eb = (int64_t*)realloc(m->eb, sizeof(int64_t) * (size_t)m->cap);
+        if (eb) m->eb = eb;
+        double* ew = (double*)realloc(m->ew, sizeof(double) * (size_t)m->cap);
+        if (ew) m->ew = ew;
+        if (!ea || !eb || !ew) return -1;
+    }
+    m->ea[m->nedge] = a;
+    m->eb[m->nedge] = b;
+    m->ew[m->nedge] = 0.0;
+    return m->nedge++;
+}
+
+/* cot of the angle at p0 between the chords to p1 and p2 */
+static double oct_cot(const oct_mesh* m, int64_t p0, int64_t p1, int64_t p2)
+{
+    const double ux = m->px[p1] - m->px[p0], uy = m->py[p1] - m->py[p0], uz = m->pz[p1] - m->pz[p0];
+    const double vx = m->px[p2] - m->px[p0], vy = m->py[p2] - m->py[p0], vz = m->pz[p2] - m->pz[p0];
+    const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+    return (ux * vx + uy * vy + uz * vz) / sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+/* A triangle's contribution: half the cotangent of each angle to the
+ * weight of the opposite edge. */
+static int oct_triangle(oct_mesh* m, int64_t a, int64_t b, int64_t c)
+{
+    const int64_t t[3] = {a, b, c};
+    for (int r = 0; r < 3; ++r) {
+        const int64_t p0 = t[r], p1 = t[(r + 1) % 3], p2 = t[(r + 2) % 3];
+        const int64_t e = oct_edge(m, p1, p2);
+        if (e < 0) return -1;
+        m->ew[e] += 0.5 * oct_cot(m, p0, p1, p2);
+    }
+    return 0;
+}
+
+static int oct_mesh_build(const orc_oct_problem* pb, oct_mesh* m)
+{
+    memset(m, 0, sizeof *m);
+    m->pb = pb;
+    const int32_t N = pb->N, nr = 2 * N;
+    const int64_t nc = orc_oct_cells(N);
+    m->nring = nr;
+    m->ncell = nc;
+    m->npts = (int32_t*)malloc(sizeof(int32_t) * nr);
+    m->first = (int64_t*)malloc(sizeof(int64_t) * nr);
+    m->lon = (double*)malloc(sizeof(double) * (size_t)nc);
+    m->lat = (double*)malloc(sizeof(double) * (size_t)nc);
+    m->px = (double*)malloc(sizeof(double) * (size_t)nc);
+    m->py = (double*)malloc(sizeof(double) * (size_t)nc);
+    m->pz = (double*)malloc(sizeof(double) * (size_t)nc);
+    m->area = (double*)calloc((size_t)nc, sizeof(double));
+    m->hcell = (double*)malloc(sizeof(double) * (size_t)nc);
+    double* mu = (double*)malloc(sizeof(double) * nr);
+    double* wg = (double*)malloc(sizeof(double) * nr);
+    if (!m->npts || !m->first || !m->lon || !m->lat || !m->px || !m->py || !m->pz || !m->area || !m->hcell ||
+        !mu || !wg) {
+        free(mu); free(wg); oct_mesh_free(m);
+        return -1;
+    }
+    orc_oct_gauss(N, mu, wg);
+    int64_t off = 0;
+    for (int j = 0; j < nr; ++j) {
+        m->npts[j] = orc_oct_ring_points(N, j);
+        m->first[j] = off;
+        const double lat = asin(mu[j]);
+        for (int q = 0; q < m->npts[j]; ++q) {
+            const int64_t c = off + q;
+            m->lat[c] = lat;
+            m->lon[c] = 2.0 * M_PI * q / m->npts[j];
+            m->px[c] = cos(lat) * cos(m->lon[c]);
+            m->py[c] = cos(lat) * sin(m->lon[c]);
+            m->pz[c] = sin(lat);
+            m->hcell[c] = oct_hill(pb, m->lon[c], lat);
+        }
+        off += m->npts[j];
+    }
+    free(mu); free(wg);
+    /* the triangles between each pair of neighbouring rings */
+    for (int j = 0; j + 1 < nr; ++j) {
+        const int64_t n = m->npts[j], n2 = m->npts[j + 1];
+        const int64_t f1 = m->first[j], f2 = m->first[j + 1];
+        int64_t a = 0, b = 0;
+        while (a < n || b < n2) {
+            int rc;
+            /* point a+1 of ring j comes no later than point b+1 of ring j+1:
+             * (a+1)/n <= (b+1)/n2, compared exactly in integers */
+            if (a < n && (b >= n2 || (a + 1) * n2 <= (b + 1) * n)) {
+                rc = oct_triangle(m, f1 + a % n, f1 + (a + 1) % n, f2 + b % n2);
+                a += 1;
+            } else {
+                rc = oct_triangle(m, f1 + a % n, f2 + b % n2, f2 + (b + 1) % n2);
+                b += 1;
+            }
+            if (rc != 0) { oct_mesh_free(m); return -1; }
+        }
+    }
+    /* Voronoi areas and the hill at every edge's centre */
+    m->eh = (double*)malloc(sizeof(double) * (size_t)(m->nedge ? m->nedge : 1));
+    if (!m->eh) { oct_mesh_free(m); return -1; }
+    for (int64_t e = 0; e < m->nedge; ++e) {
+        const int64_t a = m->ea[e], b = m->eb[e];
+        const double dx = m->px[a] - m->px[b], dy = m->py[a] - m->py[b], dz = m->pz[a] - m->pz[b];
+        const double q = 0.25 * m->ew[e] * (dx * dx + dy * dy + dz * dz);
+        m->area[a] += q;
+        m->area[b] += q;
+        const double mx = m->px[a] + m->px[b], my = m->py[a] + m->py[b], mz = m->pz[a] + m->pz[b];
+        const double r = sqrt(mx * mx + my * my + mz * mz);
+        m->eh[e] = oct_hill(pb, atan2(my, mx), asin(mz / r));
+    }
+    return 0;
+}
+
+/* The diagonal (1 + sigma) * (sum of the point's face weights) at every point
+ * and level, into d (points * nz), and the vertical weights below each level
+ * into wzb (points * (nz + 1)). */
+static void oct_weights(const oct_mesh* m, double* d, double* wzb)
+{
+    const orc_oct_problem* pb = m->pb;
+    const int64_t nc = m->ncell;
+    const double dz = pb->shell_depth / pb->nz;
+    for (int k = 0; k <= pb->nz; ++k)
+        for (int64_t c = 0; c < nc; ++c) {
+            double w = 0.0;
+            if (k > 0 && k < pb->nz) {
+                const double cc = 1.0 + pb->hill_amp * m->hcell[c] * exp(-((double)k / pb->nz) / pb->decay_z);
+                w = cc * m->area[c] / dz;
+            }
+            wzb[c + nc * k] = w;
+        }
+    for (int k = 0; k < pb->nz; ++k) {
+        const double gk = exp(-((k + 0.5) / pb->nz) / pb->decay_z);
+        double* dk = d + nc * k;
+        for (int64_t c = 0; c < nc; ++c) dk[c] = 0.0;
+        for (int64_t e = 0; e < m->nedge; ++e) {
+            const double w = (1.0 + pb->hill_amp * m->eh[e] * gk) * dz * m->ew[e];
+            dk[m->ea[e]] += w;
+            dk[m->eb[e]] += w;
+        }
+        for (int64_t c = 0; c < nc; ++c) dk[c] = (1.0 + pb->helmholtz) * (dk[c] + wzb[c + nc * k] + wzb[c + nc * (k + 1)]);
+    }
+}
+
+typedef struct {
+    oct_mesh m;
+    double* d;
+    double* wzb;
+    double* off;
+} oct_ctx;
+
+static void oct_A(const void* cx, const double* x, double* y)
+{
+    const oct_ctx* q = (const oct_ctx*)cx;
+    const oct_mesh* m = &q->m;
+    const orc_oct_problem* pb = m->pb;
+    const int64_t nc = m->ncell;
+    const double dz = pb->shell_depth / pb->nz;
+    for (int k = 0; k < pb->nz; ++k) {
+        const double gk = exp(-((k + 0.5) / pb->nz) / pb->decay_z);
+        const double* xk = x + nc * k;
+        double* off = q->off;
+        for (int64_t c = 0; c < nc; ++c) off[c] = 0.0;
+        for (int64_t e = 0; e < m->nedge; ++e) {
+            const double w = (1.0 + pb->hill_amp * m->eh[e] * gk) * dz * m->ew[e];
+            off[m->ea[e]] += w * xk[m->eb[e]];
+            off[m->eb[e]] += w * xk[m->ea[e]];
+        }
+        for (int64_t c = 0; c < nc; ++c) {
+            double o = off[c];
+            if (k > 0) o += q->wzb[c + nc * k] * x[c + nc * (k - 1)];
+            if (k < pb->nz - 1) o += q->wzb[c + nc * (k + 1)] * x[c + nc * (k + 1)];
+            y[c + nc * k] = q->d[c + nc * k] * xk[c] - o;
+        }
+    }
+}
+
+static void oct_pinv(const void* cx, const double* r, double* e)
+{
+    const oct_ctx* q = (const oct_ctx*)cx;
+    const int64_t nc = q->m.ncell;
+    const int nz = q->m.pb->nz;
+    double* gam = (double*)malloc(sizeof(double) * nz);
+    double* del = (double*)malloc(sizeof(double) * nz);
+    for (int64_t c = 0; c < nc; ++c) {
+        /* a_k e_{k-1} + b_k e_k + u_k e_{k+1} = r_k: b the diagonal of A, a and u
+         * minus the vertical face weights */
+        for (int k = 0; k < nz; ++k) {
+            const double b = q->d[c + nc * k];
+            const double a = -q->wzb[c + nc * k];
+            const double u = -q->wzb[c + nc * (k + 1)];
+            const double rk = r[c + nc * k];
+            if (k == 0) {
+                gam[0] = u / b;
+                del[0] = rk / b;
+            } else {
+                const double mk = b - a * gam[k - 1];
+                gam[k] = u / mk;
+                del[k] = (rk - a * del[k - 1]) / mk;
+            }
+        }
+        e[c + nc * (nz - 1)] = del[nz - 1];
+        for (int k = nz - 2; k >= 0; --k) e[c + nc * k] = del[k] - gam[k] * e[c + nc * (k + 1)];
+    }
+    free(gam);
+    free(del);
+}
+
+static void oct_close(oct_ctx* q)
+{
+    oct_mesh_free(&q->m);
+    free(q->d);
+    free(q->wzb);
+    free(q->off);
+}
+
+static int oct_open(const orc_oct_problem* pb, oct_ctx* q, op_pair* op)
+{
+    memset(q, 0, sizeof *q);
+    if (!pb || pb->N < 1 || pb->nz < 1) return -1;
+    if (oct_mesh_build(pb, &q->m) != 0) return -1;
+    const int64_t nc = q->m.ncell;
+    q->d = (double*)malloc(sizeof(double) * (size_t)(nc * pb->nz));
+    q->wzb = (double*)malloc(sizeof(double) * (size_t)(nc * (pb->nz + 1)));
+    q->off = (double*)malloc(sizeof(double) * (size_t)nc);
+    if (!q->d || !q->wzb || !q->off) {
+        oct_close(q);
+        return -1;
+    }
+    oct_weights(&q->m, q->d, q->wzb);
+    op->n = nc * pb->nz;
+    op->apply_A = oct_A;
+    op->apply_pinv = oct_pinv;
+    op->ctx = q;
+    return 0;
+}
+
+int orc_oct_apply_A(const orc_oct_problem* pb, const double* x, double* y)
+{
+    oct_ctx q;
+    op_pair op;
+    if (oct_open(pb, &q, &op) != 0) return -1;
+    op.apply_A(op.ctx, x, y);
+    oct_close(&q);
+    return 0;
+}
+
+int orc_oct_apply_pinv(const orc_oct_problem* pb, const double* r, double* e)
+{
+    oct_ctx q;
+    op_pair op;
+    if (oct_open(pb, &q, &op) != 0) return -1;
+    op.apply_pinv(op.ctx, r, e);
+    oct_close(&q);
+    return 0;
+}
+
+int orc_oct_mesh(const orc_oct_problem* pb, double* lon, double* lat, double* area, int64_t* nedge)
+{
+    oct_mesh m;
+    if (!pb || pb->N < 1 || oct_mesh_build(pb, &m) != 0) return -1;
+    for (int64_t c = 0; c < m.ncell; ++c) {
+        lon[c] = m.lon[c];
+        lat[c] = m.lat[c];
+        area[c] = m.area[c];
+    }
+    *nedge = m.nedge;
+    oct_mesh_free(&m);
+    return 0;
+}
+
+int orc_oct_solve(const orc_oct_problem* pb, const double* rhs, double* x, double tol,
+                  int32_t k, int64_t max_steps, int32_t ft, int32_t method,
+                  const orc_event* events, int32_t n_events, orc_stats* st,
+                  orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
+{
+    oct_ctx q;
+    op_pair op;
+    if (oct_open(pb, &q, &op) != 0) return -1;
+    const int rc = method == 1
+        ? gmres_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap)
+        : gcr_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap,
+                   NULL, NULL, 0);
+    oct_close(&q);
+    return rc;
 }

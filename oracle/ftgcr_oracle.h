@@ -149,6 +149,32 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
                     const orc_event* events, int32_t n_events, orc_stats* st,
                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
 
+/* Octahedral reduced Gaussian grid O_N (Section 3, Table 1): 2N rings of
+ * 4i + 16 points (i = 1..N from either pole), 4N(N+9) points per level, at
+ * the Gaussian latitudes, with the node-centred finite-volume operator on the
+ * triangulated mesh described above its definition.  Coefficients and shift
+ * as for the lat-lon problem. */
+typedef struct {
+    int32_t N, nz;
+    double shell_depth, hill_lon, hill_lat, hill_amp, hill_width, decay_z, helmholtz;
+} orc_oct_problem;
+
+int64_t orc_oct_cells(int32_t N);                 /* 4N(N+9), cells per level */
+int32_t orc_oct_ring_points(int32_t N, int32_t j);/* points of ring j (0 = southernmost) */
+/* The 2N Gauss-Legendre nodes (sines of the ring latitudes, ascending) and weights. */
+void orc_oct_gauss(int32_t N, double* mu, double* w);
+/* Longitude, latitude and control area of every point (4N(N+9) each), and
+ * the number of edges of the triangulation. */
+int orc_oct_mesh(const orc_oct_problem* pb, double* lon, double* lat, double* area, int64_t* nedge);
+int orc_oct_apply_A(const orc_oct_problem* pb, const double* x, double* y);
+int orc_oct_apply_pinv(const orc_oct_problem* pb, const double* r, double* e);
+/* FT-GCR(k) (method 0) or FT-GMRES(k) (method 1) on an O_N problem;
+ * arguments and outcomes as for orc_solve / orc_gmres_solve. */
+int orc_oct_solve(const orc_oct_problem* pb, const double* rhs, double* x, double tol,
+                  int32_t k, int64_t max_steps, int32_t ft, int32_t method,
+                  const orc_event* events, int32_t n_events, orc_stats* st,
+                  orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
+
 #ifdef __cplusplus
 }
 #endif

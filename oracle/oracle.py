@@ -22,7 +22,14 @@ Functions and what pins them (tests/test_oracle_*.py):
       cycles, GCR(k) on one long cycle, dense LU solutions, and predicted
       fault outcomes (x flips caught at the cycle end, overflowing v or
       A z flips at their step, both recovered bit for bit; flips of z are
-      consistent with A z and never detected).
+      consistent with A z and never detected);
+  OctOracle (the octahedral reduced Gaussian grid O_N of Section 3) --
+      the point counts and equatorial spacings of Table 1, Gauss-Legendre
+      nodes and weights against numpy, Euler's formula for the triangulation
+      and control areas against the area of the sphere, symmetry, zero row
+      sums and SPD spectra of the operator, convergence of the finite-volume
+      Laplacian to the spherical-harmonic eigenvalues, the preconditioner
+      against dense column solves, and the solvers against dense LU.
 """
 from __future__ import annotations
 
@@ -98,6 +105,23 @@ def _load():
         lib.orc_solve_traced.restype = ctypes.c_int
         lib.orc_gmres_solve.argtypes = lib.orc_solve.argtypes
         lib.orc_gmres_solve.restype = ctypes.c_int
+        OP = ctypes.POINTER(_OctProblem)
+        lib.orc_oct_cells.argtypes = [ctypes.c_int32]
+        lib.orc_oct_cells.restype = ctypes.c_int64
+        lib.orc_oct_ring_points.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        lib.orc_oct_ring_points.restype = ctypes.c_int32
+        lib.orc_oct_gauss.argtypes = [ctypes.c_int32, dp, dp]
+        lib.orc_oct_gauss.restype = None
+        lib.orc_oct_mesh.argtypes = [OP, dp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_oct_mesh.restype = ctypes.c_int
+        lib.orc_oct_apply_A.argtypes = [OP, dp, dp]
+        lib.orc_oct_apply_A.restype = ctypes.c_int
+        lib.orc_oct_apply_pinv.argtypes = [OP, dp, dp]
+        lib.orc_oct_apply_pinv.restype = ctypes.c_int
+        lib.orc_oct_solve.argtypes = [OP, dp, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.POINTER(_Event), ctypes.c_int32, ctypes.POINTER(_Stats),
+                                      ctypes.POINTER(_Detect), ctypes.c_int32, dp, ctypes.c_int64]
+        lib.orc_oct_solve.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -116,6 +140,132 @@ def _vec(a, n) -> np.ndarray:
     if a.size != n:
         raise ValueError(f"expected {n} entries, got {a.size}")
     return a
+
+
+class _OctProblem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("nz", ctypes.c_int32), ("shell_depth", ctypes.c_double),
+                ("hill_lon", ctypes.c_double), ("hill_lat", ctypes.c_double), ("hill_amp", ctypes.c_double),
+                ("hill_width", ctypes.c_double), ("decay_z", ctypes.c_double), ("helmholtz", ctypes.c_double)]
+
+
+def _events(plan, keep):
+    plan = list(plan or [])
+    events = (_Event * max(1, len(plan)))()
+    for q, ev in enumerate(plan):
+        idx = getattr(ev, "idx", None)
+        bits = getattr(ev, "bits", None)
+        e = events[q]
+        e.step, e.vec, e.bit = int(ev.step), int(ev.vec), int(ev.bit)
+        e.start = int(getattr(ev, "start", 0))
+        if idx is not None:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            keep.append(idx)
+            e.idx = idx.ctypes.data
+            e.count = idx.size
+        else:
+            e.idx = None
+            e.count = int(ev.count)
+        if bits is not None:
+            bits = np.ascontiguousarray(bits, dtype=np.uint8)
+            keep.append(bits)
+            e.bits = bits.ctypes.data
+        else:
+            e.bits = None
+    return events, len(plan)
+
+
+class OctOracle:
+    """FP64 reference of the octahedral O_N operator, its column
+    preconditioner and FT-GCR(k) / FT-GMRES(k) on it.  `problem` has N, nz
+    and the coefficient fields of the lat-lon problems (shell_depth,
+    hill_lon, hill_lat, hill_amp, hill_width, decay_z, helmholtz)."""
+
+    def __init__(self, problem):
+        self.problem = problem
+        pb = problem
+        self._c = _OctProblem(pb.N, pb.nz, pb.shell_depth, pb.hill_lon, pb.hill_lat, pb.hill_amp,
+                              pb.hill_width, pb.decay_z, pb.helmholtz)
+        lib = _load()
+        self.cells = int(lib.orc_oct_cells(pb.N))
+
+    @property
+    def n(self) -> int:
+        return self.cells * self.problem.nz
+
+    def ring_points(self):
+        return np.array([_load().orc_oct_ring_points(self.problem.N, j) for j in range(2 * self.problem.N)])
+
+    def gauss(self):
+        m = 2 * self.problem.N
+        mu, w = np.empty(m), np.empty(m)
+        _load().orc_oct_gauss(self.problem.N, _ptr(mu), _ptr(w))
+        return mu, w
+
+    def mesh(self):
+        """Longitude, latitude and control area of every point, and the
+        number of edges of the triangulation."""
+        m = self.cells
+        lon, lat, area = np.empty(m), np.empty(m), np.empty(m)
+        ne = ctypes.c_int64()
+        if _load().orc_oct_mesh(ctypes.byref(self._c), _ptr(lon), _ptr(lat), _ptr(area), ctypes.byref(ne)) != 0:
+            raise ValueError("bad O_N problem")
+        return lon, lat, area, int(ne.value)
+
+    def apply_A(self, x) -> np.ndarray:
+        x = _vec(x, self.n)
+        y = np.empty(self.n)
+        if _load().orc_oct_apply_A(ctypes.byref(self._c), _ptr(x), _ptr(y)) != 0:
+            raise ValueError("bad O_N problem")
+        return y
+
+    def apply_pinv(self, r) -> np.ndarray:
+        r = _vec(r, self.n)
+        e = np.empty(self.n)
+        if _load().orc_oct_apply_pinv(ctypes.byref(self._c), _ptr(r), _ptr(e)) != 0:
+            raise ValueError("bad O_N problem")
+        return e
+
+    def dense_matrix(self) -> np.ndarray:
+        n = self.n
+        if n > 4096:
+            raise ValueError("dense assembly is for tiny grids")
+        m = np.empty((n, n))
+        unit = np.zeros(n)
+        for c in range(n):
+            unit[c] = 1.0
+            m[:, c] = self.apply_A(unit)
+            unit[c] = 0.0
+        return m
+
+    def dot(self, a, b) -> float:
+        return _load().orc_dot(self.n, _ptr(_vec(a, self.n)), _ptr(_vec(b, self.n)))
+
+    def solve(self, rhs, x0=None, tol: float = 1e-10, k: int = 3, max_steps: int = 100000, ft: bool = True,
+              plan=None, log_cap: int = 4096, hist_cap: Optional[int] = None, method: str = "gcr"):
+        """FT-GCR(k) or FT-GMRES(k) on the O_N problem; returns (x, stats,
+        detection log, residual history) as Oracle.solve."""
+        rhs = _vec(rhs, self.n)
+        x = np.zeros(self.n) if x0 is None else _vec(x0, self.n).copy()
+        keep = []
+        events, nev = _events(plan, keep)
+        if hist_cap is None:
+            hist_cap = min(max_steps, 1 << 20)
+        hist = np.zeros(max(1, hist_cap))
+        log = (_Detect * max(1, log_cap))()
+        st = _Stats()
+        rc = _load().orc_oct_solve(ctypes.byref(self._c), _ptr(rhs), _ptr(x), float(tol), int(k), int(max_steps),
+                                   1 if ft else 0, {"gcr": 0, "gmres": 1}[method], events, nev, ctypes.byref(st),
+                                   log, int(log_cap), _ptr(hist), int(hist_cap))
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        stats = {name: getattr(st, name) for name, _ in _Stats._fields_ if name != "pad_"}
+        dlog = [dict(step=log[t].step, nu=log[t].nu, action=log[t].action,
+                     rr_old=log[t].rr_old, rr_new=log[t].rr_new) for t in range(st.log_len)]
+        return x, stats, dlog, hist[: st.hist_len].copy()
+
+    def true_residual(self, x, rhs) -> float:
+        r = self.apply_A(x) - _vec(rhs, self.n)
+        return float(np.sqrt(self.dot(r, r) / self.dot(rhs, rhs)))
 
 
 class Oracle:
