@@ -20,7 +20,8 @@
  *
  * Conventions
  *  - Every field is a contiguous C-order array [nz][nlat][nlon] (longitude
- *    fastest); flat index of cell (i, j, k) is i + nlon*(j + nlat*k).
+ *    fastest); flat index of cell (i, j, k) is i + nlon*(j + nlat*k).  On the
+ *    octahedral mesh, [nz][points]: point p of level k is p + points*k.
  *  - Device pointers are HIP device memory of the handle's device; the
  *    caller owns them.  Host pointers (plans, stats, logs) are read or written
  *    only during the call.
@@ -61,11 +62,31 @@ enum { FTGCR_CONVERGED = 0, FTGCR_MAX_STEPS = 1, FTGCR_STAGNATED = 2, FTGCR_BREA
 /* Capacity of the device-side detection log per solve. */
 #define FTGCR_LOG_CAP 256
 
+/* Meshes (ftgcr_grid.mesh).
+ * LATLON: nlon x nlat cell centres of a regular longitude-latitude grid,
+ *   the 7-point flux form described at the top of this file.
+ * OCTAHEDRAL: the octahedral reduced Gaussian grid O_N of the paper's
+ *   experiments (Section 3, Table 1), N = nlat (nlon is ignored): 2N rings at
+ *   the Gaussian latitudes (the sines are the roots of the Legendre
+ *   polynomial P_2N), the i-th ring from either pole (i = 1..N) with 4i + 16
+ *   equally spaced points starting at longitude 0, 4N(N+9) points per level,
+ *   numbered ring by ring from the south pole, eastward, then level by
+ *   level.  Node-centred finite volumes on the triangulation that joins
+ *   neighbouring rings (walking both eastward from longitude 0, the ring whose
+ *   next point comes first -- the southern one on a tie -- adds a triangle;
+ *   the polar caps stay open: no flux through the poles): the control area
+ *   of a point is its circumcentric region of the inscribed polyhedron, the
+ *   horizontal face weight of an edge is c dz (cot a + cot b) / 2 (the angles
+ *   opposite it), the vertical ones c area / dz, c at the face centre.  FP64
+ *   handles, FT-GCR, single solves. */
+enum { FTGCR_MESH_LATLON = 0, FTGCR_MESH_OCTAHEDRAL = 1 };
+
 typedef struct {
-    int32_t nlon;          /* >= 3                                              */
-    int32_t nlat;          /* >= 1                                              */
+    int32_t nlon;          /* LATLON: >= 3; OCTAHEDRAL: ignored                 */
+    int32_t nlat;          /* LATLON: >= 1; OCTAHEDRAL: N >= 1                  */
     int32_t nz;            /* 1 .. 96 with the column preconditioner            */
     double shell_depth;    /* vertical extent of the shell, unit sphere; > 0    */
+    int32_t mesh;          /* FTGCR_MESH_LATLON (0) or FTGCR_MESH_OCTAHEDRAL    */
 } ftgcr_grid;
 
 typedef struct {

@@ -817,6 +817,8 @@ typedef struct {
     double* hcell;        /* hill height at each point                    */
     int64_t nedge, cap;
     int64_t *ea, *eb;     /* edge ends                                    */
+    int64_t* inc;         /* incident edges of every point, OCT_INC each  */
+    int32_t* ninc;
     double* ew;           /* (cot alpha + cot beta) / 2                   */
     double* eh;           /* hill height at the edge's centre             */
 } oct_mesh;
@@ -831,19 +833,23 @@ static double oct_hill(const orc_oct_problem* pb, double lon, double lat)
     return orc_hill(&q, lon, lat);
 }
 
+enum { OCT_INC = 16 };   /* room for incident edges per point (the mesh has at most 6) */
+
 static void oct_mesh_free(oct_mesh* m)
 {
     free(m->npts); free(m->first); free(m->lon); free(m->lat); free(m->px); free(m->py); free(m->pz);
     free(m->area); free(m->hcell); free(m->ea); free(m->eb); free(m->ew); free(m->eh);
+    free(m->inc); free(m->ninc);
 }
 
-/* Index of edge (a, b), added if new (linear search: plain, not fast). */
+/* Index of edge (a, b), added if new (a search of a's incident edges). */
 static int64_t oct_edge(oct_mesh* m, int64_t a, int64_t b)
 {
-    for (int64_t e = m->nedge - 1; e >= 0 && e >= m->nedge - 64; --e)
+    for (int32_t q = 0; q < m->ninc[a]; ++q) {
+        const int64_t e = m->inc[a * OCT_INC + q];
         if ((m->ea[e] == a && m->eb[e] == b) || (m->ea[e] == b && m->eb[e] == a)) return e;
-    for (int64_t e = 0; e < m->nedge; ++e)
-        if ((m->ea[e] == a && m->eb[e] == b) || (m->ea[e] == b && m->eb[e] == a)) return e;
+    }
+    if (m->ninc[a] == OCT_INC || m->ninc[b] == OCT_INC) return -1;
     if (m->nedge == m->cap) {
         m->cap = m->cap ? 2 * m->cap : 1024;
         int64_t* ea = (int64_t*)realloc(m->ea, sizeof(int64_t) * (size_t)m->cap);
@@ -857,6 +863,8 @@ static int64_t oct_edge(oct_mesh* m, int64_t a, int64_t b)
     m->ea[m->nedge] = a;
     m->eb[m->nedge] = b;
     m->ew[m->nedge] = 0.0;
+    m->inc[a * OCT_INC + m->ninc[a]++] = m->nedge;
+    m->inc[b * OCT_INC + m->ninc[b]++] = m->nedge;
     return m->nedge++;
 }
 
@@ -900,10 +908,12 @@ static int oct_mesh_build(const orc_oct_problem* pb, oct_mesh* m)
     m->pz = (double*)malloc(sizeof(double) * (size_t)nc);
     m->area = (double*)calloc((size_t)nc, sizeof(double));
     m->hcell = (double*)malloc(sizeof(double) * (size_t)nc);
+    m->inc = (int64_t*)malloc(sizeof(int64_t) * (size_t)nc * OCT_INC);
+    m->ninc = (int32_t*)calloc((size_t)nc, sizeof(int32_t));
     double* mu = (double*)malloc(sizeof(double) * nr);
     double* wg = (double*)malloc(sizeof(double) * nr);
     if (!m->npts || !m->first || !m->lon || !m->lat || !m->px || !m->py || !m->pz || !m->area || !m->hcell ||
-        !mu || !wg) {
+        !m->inc || !m->ninc || !mu || !wg) {
         free(mu); free(wg); oct_mesh_free(m);
         return -1;
     }

@@ -176,8 +176,13 @@ void set_tiling(ftgcr_handle* h)
     const Geo& g = h->geo;
     const int cpb = col_block_cols(h->precision == FTGCR_MIXED ? 4 : 8, h->H);
     h->nblk_col = (g.ncols + cpb - 1) / cpb;
-    h->tx = (g.nx + ST_TX - 1) / ST_TX;
-    h->ty = (g.ny + ST_TY - 1) / ST_TY;
+    if (g.mesh == FTGCR_MESH_OCTAHEDRAL) {   // ST_THREADS consecutive points per block
+        h->tx = (g.nx + ST_THREADS - 1) / ST_THREADS;
+        h->ty = 1;
+    } else {
+        h->tx = (g.nx + ST_TX - 1) / ST_TX;
+        h->ty = (g.ny + ST_TY - 1) / ST_TY;
+    }
     int kc = h->opt.levels_per_block;
     if (kc != 1 && kc != 2 && kc != 4 && kc != 8 && kc != 16) kc = h->tuned_kc ? h->tuned_kc : tuned_levels(h);
     if (kc != 1 && kc != 2 && kc != 4 && kc != 8 && kc != 16) kc = auto_levels_per_block(h->tx, h->ty, g.nz);
@@ -287,6 +292,7 @@ ftgcr_status upload_tables(ftgcr_handle* h)
     float* tab32 = reinterpret_cast<float*>(h->tables + total);
     HIP_TRY(h, hipMemcpy(tab32, t32.data(), n32 * sizeof(float), hipMemcpyHostToDevice));
     Geo& g = h->geo;
+    g.mesh = FTGCR_MESH_LATLON;
     g.nx = nx;
     g.ny = ny;
     g.nz = nz;
@@ -304,6 +310,179 @@ ftgcr_status upload_tables(ftgcr_handle* h)
     g.hx32 = tab32;
     g.hy32 = g.hx32 + nhx;
     g.hc32 = g.hy32 + nhy;
+    return FTGCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// octahedral reduced Gaussian grid O_N: host tables
+// ---------------------------------------------------------------------------
+
+// Points per level of O_N and of its ring j (0 = southernmost).
+long long oct_points(int N) { return 4LL * N * (N + 9); }
+int oct_ring(int N, int j) { return 4 * (j < N ? j + 1 : 2 * N - j) + 16; }
+
+// Gauss-Legendre nodes of order n (ascending) by Newton's method on the
+// Legendre recurrence, started from Tricomi's asymptotic estimate.
+std::vector<double> gauss_nodes(int n)
+{
+    std::vector<double> mu(n);
+    for (int l = 1; l <= n; ++l) {
+        const double th = kPi * (4.0 * l - 1.0) / (4.0 * n + 2.0);
+        double x = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th);
+        for (int it = 0; it < 50; ++it) {
+            double pm = 1.0, p = x;   // P_0, P_1
+            for (int m = 2; m <= n; ++m) {
+                const double pn = ((2 * m - 1) * x * p - (m - 1) * pm) / m;
+                pm = p;
+                p = pn;
+            }
+            const double dpdx = n * (pm - x * p) / (1.0 - x * x);
+            const double step = p / dpdx;
+            x -= step;
+            if (std::fabs(step) <= 1e-16 * std::fabs(x) + 1e-300) break;
+        }
+        mu[n - l] = x;   // the l-th largest root
+    }
+    return mu;
+}
+
+ftgcr_status upload_tables_oct(ftgcr_handle* h)
+{
+    const int N = h->grid.nlat, nz = h->grid.nz, nr = 2 * N;
+    const long long np = oct_points(N);
+    const double dz = h->grid.shell_depth / nz;
+    const ftgcr_coeffs& co = h->co;
+    const std::vector<double> mu = gauss_nodes(nr);
+    std::vector<long long> first(nr + 1, 0);
+    for (int j = 0; j < nr; ++j) first[j + 1] = first[j] + oct_ring(N, j);
+    if (first[nr] != np) return fail(h, FTGCR_E_HIP, "octahedral point count");
+    std::vector<double> px(np), py(np), pz(np), plon(np), plat(np);
+    for (int j = 0; j < nr; ++j) {
+        const int n = oct_ring(N, j);
+        const double lat = std::asin(mu[j]);
+        for (int q = 0; q < n; ++q) {
+            const long long a = first[j] + q;
+            const double lon = (2.0 * kPi / n) * q;
+            plon[a] = lon;
+            plat[a] = lat;
+            px[a] = std::cos(lat) * std::cos(lon);
+            py[a] = std::cos(lat) * std::sin(lon);
+            pz[a] = std::sin(lat);
+        }
+    }
+    // neighbour slots: ids (-1 empty) and accumulated cotangent weights
+    std::vector<int> nb((size_t)np * NB_OCT, -1);
+    std::vector<double> cw((size_t)np * NB_OCT, 0.0);
+    auto slot = [&](long long a, long long b) -> long long {
+        for (int q = 0; q < NB_OCT; ++q) {
+            const size_t at = (size_t)a * NB_OCT + q;
+            if (nb[at] == (int)b) return (long long)at;
+            if (nb[at] < 0) {
+                nb[at] = (int)b;
+                return (long long)at;
+            }
+        }
+        return -1;
+    };
+    bool overflow = false;
+    // a triangle adds half the cotangent of each corner to the opposite edge
+    auto triangle = [&](long long a, long long b, long long c) {
+        const long long v[3] = {a, b, c};
+        for (int r = 0; r < 3; ++r) {
+            const long long o = v[r], e1 = v[(r + 1) % 3], e2 = v[(r + 2) % 3];
+            const double ux = px[e1] - px[o], uy = py[e1] - py[o], uz = pz[e1] - pz[o];
+            const double vx = px[e2] - px[o], vy = py[e2] - py[o], vz = pz[e2] - pz[o];
+            const double dot = ux * vx + uy * vy + uz * vz;
+            const double crx = uy * vz - uz * vy, cry = uz * vx - ux * vz, crz = ux * vy - uy * vx;
+            const double half_cot = 0.5 * dot / std::sqrt(crx * crx + cry * cry + crz * crz);
+            const long long s1 = slot(e1, e2), s2 = slot(e2, e1);
+            if (s1 < 0 || s2 < 0) {
+                overflow = true;
+                return;
+            }
+            cw[s1] += half_cot;
+            cw[s2] += half_cot;
+        }
+    };
+    for (int j = 0; j + 1 < nr; ++j) {
+        const long long n = oct_ring(N, j), n2 = oct_ring(N, j + 1);
+        long long a = 0, b = 0;
+        // eastward: the ring whose next point comes first adds a triangle
+        // ((a+1)/n <= (b+1)/n2 in exact integer form; the southern ring on a tie)
+        while (a < n || b < n2) {
+            if (a < n && (b >= n2 || (a + 1) * n2 <= (b + 1) * n)) {
+                triangle(first[j] + a % n, first[j] + (a + 1) % n, first[j + 1] + b % n2);
+                ++a;
+            } else {
+                triangle(first[j] + a % n, first[j + 1] + b % n2, first[j + 1] + (b + 1) % n2);
+                ++b;
+            }
+        }
+    }
+    if (overflow) return fail(h, FTGCR_E_HIP, "octahedral mesh: a point has more than NB_OCT neighbours");
+    // per point: slot tables (slot-major), sums, circumcentric area, hills
+    const size_t nq = (size_t)NB_OCT * np;
+    std::vector<int> onb(nq);
+    std::vector<double> ogw(nq), ohw(nq), oh0(np), oh1(np), ogz(np), ohc(np);
+    for (long long a = 0; a < np; ++a) {
+        double area = 0.0, s0 = 0.0, s1 = 0.0;
+        for (int q = 0; q < NB_OCT; ++q) {
+            const size_t at = (size_t)a * NB_OCT + q;
+            const size_t to = (size_t)q * np + a;
+            const int b = nb[at];
+            onb[to] = b;
+            ogw[to] = 0.0;
+            ohw[to] = 0.0;
+            if (b < 0) continue;
+            const double dx = px[a] - px[b], dy = py[a] - py[b], dzz = pz[a] - pz[b];
+            area += 0.25 * cw[at] * (dx * dx + dy * dy + dzz * dzz);
+            // hill at the edge's centre: the chord's midpoint, back on the sphere
+            const double mx = px[a] + px[b], my = py[a] + py[b], mz = pz[a] + pz[b];
+            const double mr = std::sqrt(mx * mx + my * my + mz * mz);
+            const double he = co.hill_amp * hill_height(co, std::atan2(my, mx), std::asin(mz / mr));
+            ogw[to] = dz * cw[at];
+            ohw[to] = ogw[to] * he;
+            s0 += ogw[to];
+            s1 += ohw[to];
+        }
+        oh0[a] = s0;
+        oh1[a] = s1;
+        ogz[a] = area / dz;
+        ohc[a] = co.hill_amp * hill_height(co, plon[a], plat[a]);
+    }
+    std::vector<double> gc(nz), gf(nz + 1);
+    for (int k = 0; k < nz; ++k) gc[k] = std::exp(-((k + 0.5) / nz) / co.decay_z);
+    for (int k = 0; k <= nz; ++k) gf[k] = std::exp(-((double)k / nz) / co.decay_z);
+    // one device allocation: doubles first, then the slot ids
+    const size_t nd = 2 * nq + 4 * (size_t)np + nz + (nz + 1);
+    HIP_TRY(h, hipMalloc(&h->tables, nd * sizeof(double) + nq * sizeof(int)));
+    double* t = h->tables;
+    auto put = [&](const double* src, size_t cnt) -> double* {
+        double* at = t;
+        t += cnt;
+        return hipMemcpy(at, src, cnt * sizeof(double), hipMemcpyHostToDevice) == hipSuccess ? at : nullptr;
+    };
+    Geo& g = h->geo;
+    g.mesh = FTGCR_MESH_OCTAHEDRAL;
+    g.nx = (int)np;
+    g.ny = 1;
+    g.nz = nz;
+    g.ncols = (int)np;
+    g.n = np * nz;
+    g.opsig = 1.0 + co.helmholtz;
+    g.ogw = put(ogw.data(), nq);
+    g.ohw = put(ohw.data(), nq);
+    g.oh0 = put(oh0.data(), np);
+    g.oh1 = put(oh1.data(), np);
+    g.ogz = put(ogz.data(), np);
+    g.ohc = put(ohc.data(), np);
+    g.gc = put(gc.data(), nz);
+    g.gf = put(gf.data(), nz + 1);
+    int* ids = reinterpret_cast<int*>(t);
+    HIP_TRY(h, hipMemcpy(ids, onb.data(), nq * sizeof(int), hipMemcpyHostToDevice));
+    g.onb = ids;
+    if (!g.ogw || !g.ohw || !g.oh0 || !g.oh1 || !g.ogz || !g.ohc || !g.gc || !g.gf)
+        return fail(h, FTGCR_E_HIP, "octahedral table upload failed");
     return FTGCR_OK;
 }
 
@@ -679,7 +858,7 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     h->nt_ap = nt_ap_hint(k, h->geo.n, (int)sizeof(T));
     HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1}, s};
+    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh}, s};
     run.noalloc = staging != nullptr;
     const Table<T>& tb = run.tb;
     const bool mixed = h->precision == FTGCR_MIXED;
@@ -1251,7 +1430,15 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
     if (!out) return fail(nullptr, FTGCR_E_INVALID, "out == NULL");
     *out = nullptr;
     if (!grid || !coeffs) return fail(nullptr, FTGCR_E_INVALID, "grid or coeffs == NULL");
-    if (grid->nlon < 3 || grid->nlat < 1 || grid->nz < 1) return fail(nullptr, FTGCR_E_INVALID, "grid needs nlon >= 3, nlat >= 1, nz >= 1");
+    if (grid->mesh != FTGCR_MESH_LATLON && grid->mesh != FTGCR_MESH_OCTAHEDRAL)
+        return fail(nullptr, FTGCR_E_INVALID, "grid.mesh must be FTGCR_MESH_LATLON or FTGCR_MESH_OCTAHEDRAL");
+    const bool oct = grid->mesh == FTGCR_MESH_OCTAHEDRAL;
+    if (!oct && (grid->nlon < 3 || grid->nlat < 1 || grid->nz < 1))
+        return fail(nullptr, FTGCR_E_INVALID, "grid needs nlon >= 3, nlat >= 1, nz >= 1");
+    if (oct && (grid->nlat < 1 || grid->nlat > 4000 || grid->nz < 1))
+        return fail(nullptr, FTGCR_E_INVALID, "octahedral grid needs N = nlat in 1..4000 and nz >= 1");
+    if (oct && precision != FTGCR_FP64)
+        return fail(nullptr, FTGCR_E_UNSUPPORTED, "the octahedral mesh is built for FP64 handles");
     if (!(grid->shell_depth > 0)) return fail(nullptr, FTGCR_E_INVALID, "shell_depth must be > 0");
     if (!(coeffs->hill_width > 0) || !(coeffs->decay_z > 0) || !(coeffs->hill_amp >= 0) || !(coeffs->helmholtz > 0))
         return fail(nullptr, FTGCR_E_INVALID, "coefficients need hill_width > 0, decay_z > 0, hill_amp >= 0, helmholtz > 0");
@@ -1260,7 +1447,7 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
     if (precond != FTGCR_PRECOND_COLUMN)
         return fail(nullptr, FTGCR_E_UNSUPPORTED, "only the column preconditioner is built");
     if (thomas_depth(grid->nz) < 0) return fail(nullptr, FTGCR_E_UNSUPPORTED, "nz > 96 is not supported");
-    const long long ncols = (long long)grid->nlon * grid->nlat;
+    const long long ncols = oct ? oct_points(grid->nlat) : (long long)grid->nlon * grid->nlat;
     if (ncols > (1LL << 30) || ncols * grid->nz > (1LL << 40)) return fail(nullptr, FTGCR_E_UNSUPPORTED, "grid too large");
 
     ftgcr_handle* h = new (std::nothrow) ftgcr_handle();
@@ -1281,7 +1468,7 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
         h->err = "hipGetDevice failed";
         return bail(FTGCR_E_HIP);
     }
-    ftgcr_status rc = upload_tables(h);
+    ftgcr_status rc = oct ? upload_tables_oct(h) : upload_tables(h);
     if (rc != FTGCR_OK) return bail(rc);
     h->H = thomas_depth(grid->nz);
     set_tiling(h);
@@ -1316,6 +1503,8 @@ ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt)
         return fail(h, FTGCR_E_INVALID, "invalid options");
     if (opt->method == FTGCR_METHOD_GMRES && h->precision != FTGCR_FP64)
         return fail(h, FTGCR_E_UNSUPPORTED, "FT-GMRES is built for FP64 handles");
+    if (opt->method == FTGCR_METHOD_GMRES && h->geo.mesh != FTGCR_MESH_LATLON)
+        return fail(h, FTGCR_E_UNSUPPORTED, "FT-GMRES is built for the lat-lon mesh");
     h->opt = *opt;
     set_tiling(h);
     if (h->graph) {
@@ -1408,6 +1597,8 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
         if (h->precision != FTGCR_FP64) return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are FP64 only");
         if (h->opt.method != FTGCR_METHOD_GCR)
             return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves run FT-GCR (options.method of every member)");
+        if (h->geo.mesh != FTGCR_MESH_LATLON)
+            return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are built for the lat-lon mesh");
         if (!rhs[m] || !x[m]) return fail(hs[0], FTGCR_E_INVALID, "rhs or x is NULL");
         if (!(tol[m] > 0) || !std::isfinite(tol[m])) return fail(hs[0], FTGCR_E_INVALID, "tol must be finite and > 0");
         if (k < 1 || k > h->kmax) return fail(hs[0], FTGCR_E_INVALID, "k must be in [1, kmax] of every member");
@@ -1633,7 +1824,7 @@ ftgcr_status ftgcr_debug_apply_A(ftgcr_handle* h, const double* in_dev, double* 
     if (!h) return FTGCR_E_INVALID;
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
-    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh};
     Launch<double>::debug_apply_A(tb, h->nblk_st, h->kc, in_dev, out_dev, h->stream);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -1645,7 +1836,7 @@ ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, doubl
     if (!h) return FTGCR_E_INVALID;
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
-    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh};
     // the FP64 two-lane kernel, whatever the handle's own column tiling
     Launch<double>::debug_pinv(tb, (h->geo.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK, h->H, in_dev, out_dev,
                                h->stream);

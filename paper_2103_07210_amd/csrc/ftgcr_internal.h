@@ -39,6 +39,10 @@ constexpr int ST_TX = 64;
 constexpr int ST_TY = 4;
 constexpr int ST_THREADS = ST_TX * ST_TY;
 constexpr int RED_THREADS = 1024;
+// Octahedral mesh: neighbour slots per point (the triangulation's valence
+// is at most 6); a block of the stencil kernels covers ST_THREADS
+// consecutive points.
+constexpr int NB_OCT = 6;
 
 struct DetectRec {
     long long step;
@@ -109,6 +113,20 @@ struct Geo {
     const float* hx32;
     const float* hy32;
     const float* hc32;
+    // octahedral mesh (mesh == FTGCR_MESH_OCTAHEDRAL; then nx = points per
+    // level, ny = 1): per point and neighbour slot q (slot-major, [q][point])
+    // the neighbour (-1: empty slot), the metric part of the face weight and
+    // that times hill_amp * h at the face centre; per point the sums of both
+    // over its slots, the vertical face metric (control area / dz) and
+    // hill_amp * h at the point
+    int mesh;
+    const int* onb;
+    const double* ogw;
+    const double* ohw;
+    const double* oh0;
+    const double* oh1;
+    const double* ogz;
+    const double* ohc;
 };
 
 // Everything one instance's kernels need (device copy per solve).
@@ -187,6 +205,7 @@ struct Table {
     const int* blk0_st;      // n + 1 prefix sums (stencil grid)
     const int* blk0_dir;     // n + 1 prefix sums (direction-pass grid)
     int n;
+    int mesh = 0;            // every instance's mesh (FTGCR_MESH_*)
 };
 
 // Kernel launchers (kernels.hip).

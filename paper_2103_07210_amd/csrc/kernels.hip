@@ -300,6 +300,24 @@ __device__ __forceinline__ typename RowOf<AT>::type row_consts_for(const Geo& g,
     else return row_consts(col_weights(g, i, j));
 }
 
+// Row constants of the column solve on either mesh: the octahedral mesh
+// reads its per-point sums (only h0, h1, gz and hc are used by the solve).
+template <typename AT>
+__device__ __forceinline__ typename RowOf<AT>::type col_consts_for(const Geo& g, int i, int j)
+{
+    if constexpr (sizeof(AT) == 8) {
+        if (g.mesh == FTGCR_MESH_OCTAHEDRAL) {
+            RowC r = {};
+            r.h0 = g.oh0[i];
+            r.h1 = g.oh1[i];
+            r.gz = g.ogz[i];
+            r.hc = g.ohc[i];
+            return r;
+        }
+    }
+    return row_consts_for<AT>(g, i, j);
+}
+
 __device__ __forceinline__ float vface(const RowCf& r, float gf, int f, int nz)
 {
     return (f > 0 && f < nz) ? r.gz * fmaf(r.hc, gf, 1.0f) : 0.0f;
@@ -517,6 +535,103 @@ __device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb)
     return st_pos(in, lb, in.kc);
 }
 
+// Position on either mesh: lat-lon as above; octahedral (nx = points per
+// level, ny = 1): ST_THREADS consecutive points per block, i = the point.
+template <int MESH, typename T>
+__device__ __forceinline__ StPos st_pos_m(const Inst<T>& in, int lb, int kc)
+{
+    if constexpr (MESH == FTGCR_MESH_OCTAHEDRAL) {
+        StPos p;
+        const int bx = lb % in.tx;
+        const int bz = lb / in.tx;
+        const int i = bx * ST_THREADS + threadIdx.x;
+        p.col_ok = i < in.g.nx;
+        p.i = p.col_ok ? i : in.g.nx - 1;
+        p.j = 0;
+        p.k0 = bz * kc;
+        return p;
+    } else {
+        return st_pos(in, lb, kc);
+    }
+}
+
+// (A x) at levels k0 .. k0+KC-1 of point c of the octahedral mesh, in the
+// same operation order as a lat-lon row (off-diagonal sums of metric and
+// metric-times-hill terms, combined with g_k; diagonal h0 + g_k h1 plus the
+// vertical faces, as the column solve forms it), neighbours gathered through
+// the slot tables; an empty slot contributes a selected 0, not a product.
+template <int KC>
+__device__ __forceinline__ void stencil_oct(const Geo& g, const double* __restrict__ x, int c, int k0,
+                                            double (&out)[KC], double* centre = nullptr)
+{
+    const int nz = g.nz;
+    const long long plane = (long long)g.ncols;
+    const double h0 = g.oh0[c], h1 = g.oh1[c], gz = g.ogz[c], hc = g.ohc[c];
+    double xv[KC + 2], t1[KC], t2[KC];
+#pragma unroll
+    for (int t = 0; t < KC + 2; ++t) {
+        int k = k0 - 1 + t;
+        k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
+        xv[t] = x[c + plane * k];
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        t1[kk] = 0.0;
+        t2[kk] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NB_OCT; ++q) {
+        const long long slot = (long long)q * g.ncols + c;
+        const int nb = g.onb[slot];
+        const double gw = g.ogw[slot], hw = g.ohw[slot];
+        const long long base = nb >= 0 ? nb : c;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
+            const double v = x[base + plane * k];
+            const double vs = nb >= 0 ? v : 0.0;
+            t1[kk] = fma(gw, vs, t1[kk]);
+            t2[kk] = fma(hw, vs, t2[kk]);
+        }
+    }
+    double wf[KC + 1];
+#pragma unroll
+    for (int t = 0; t <= KC; ++t) {
+        const int f = k0 + t;
+        const int fq = f > nz ? nz : f;
+        wf[t] = (f > 0 && f < nz) ? gz * fma(hc, g.gf[fq], 1.0) : 0.0;
+    }
+    const double opsig = g.opsig;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const int k = k0 + kk;
+        const int kq = (k > nz - 1) ? nz - 1 : k;
+        const double gk = g.gc[kq];
+        const double wb = wf[kk], wa = wf[kk + 1];
+        const double xb = (k > 0) ? xv[kk] : 0.0;
+        const double xa = (k + 1 < nz) ? xv[kk + 2] : 0.0;
+        double off = fma(gk, t2[kk], t1[kk]);
+        off = fma(wb, xb, off);
+        off = fma(wa, xa, off);
+        const double diag = opsig * ((fma(gk, h1, h0) + wb) + wa);
+        out[kk] = fma(diag, xv[kk + 1], -off);
+        if (centre) centre[kk] = xv[kk + 1];
+    }
+}
+
+// The stencil on either mesh (the octahedral one is FP64 only).
+template <typename TI, int KC, int MESH>
+__device__ __forceinline__ void stencil_m(const Geo& g, const TI* __restrict__ x, const StPos& ps, double (&out)[KC],
+                                          double* centre = nullptr)
+{
+    if constexpr (MESH == FTGCR_MESH_OCTAHEDRAL) {
+        static_assert(sizeof(TI) == 8, "octahedral mesh: FP64");
+        stencil_oct<KC>(g, x, ps.i, ps.k0, out, centre);
+    } else {
+        stencil_chunk<TI, KC>(g, x, ps.i, ps.j, ps.k0, out, centre);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void write_xor(T* p, int bit);
 
@@ -609,20 +724,20 @@ __global__ void k_set_round(Table<T> tb, double tol2, long long max_steps)
 
 // r = A x - R (x = caller's FP64 iterate), stored in R[r_dst] when `store`;
 // partials of <R, R> and of the unrounded FP64 <r, r>.
-template <typename T, int KC>
+template <typename T, int KC, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
 {
     __shared__ double sh[4];
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
-    const StPos ps = st_pos(in, lb);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     T* rout = in.R[in.st->r_dst];
     const double* rhs = in.rhs;
     double ax[KC], b[KC];
-    stencil_chunk<double, KC>(in.g, in.X[0], ps.i, ps.j, ps.k0, ax);
+    stencil_m<double, KC, MESH>(in.g, in.X[0], ps, ax);
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
@@ -930,7 +1045,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     const int nmine = upper ? nup : h;
     // diagonal h0 + g_k h1 + vertical faces, from the same per-column
     // constants and in the same order as the stencil rows (identical)
-    const typename RowOf<CT>::type rcst = row_consts_for<CT>(g, i, j);
+    const typename RowOf<CT>::type rcst = col_consts_for<CT>(g, i, j);
     const CT h0 = rcst.h0;
     const CT h1 = rcst.h1;
     const CT gz = rcst.gz, hc = rcst.hc;
@@ -1248,7 +1363,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mod
 // afterwards); it runs whenever the column pass ran, and its partials are
 // discarded if the step is rejected or ends the solve.  Nothing it reads
 // (nu, the slots, e, the L(p^l)) is changed by the decision.
-template <typename T, int KC>
+template <typename T, int KC, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb, int spec)
 {
     __shared__ double sh[KMAX + 1][4];
@@ -1261,12 +1376,12 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb, int sp
     const int nu = st->nu;
     if ((int)threadIdx.x <= nu) s_ap[threadIdx.x] = in.AP[st->slot[threadIdx.x]];
     __syncthreads();
-    const StPos ps = st_pos(in, lb);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double le[KC];
-    stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, le);
+    stencil_m<T, KC, MESH>(in.g, in.E, ps, le);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
         if (!(ps.col_ok && ps.k0 + kk < nz)) le[kk] = 0.0;
@@ -1380,7 +1495,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_step(Table<T> tb)
 // NTAP extends the hint to the L(p^l) loads: set when the solve's k + 1
 // images of A p do not fit the cache anyway (otherwise the next dots pass
 // finds them there).
-template <typename T, int KC, bool NTAP>
+template <typename T, int KC, bool NTAP, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init)
 {
     __shared__ double sh[4];
@@ -1411,13 +1526,13 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
         s_be[threadIdx.x] = (xupd && (int)threadIdx.x >= xlo) ? st->beta[threadIdx.x] : 0.0;
     }
     __syncthreads();
-    const StPos ps = st_pos(in, lb, in.kc_dir);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc_dir);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double a[KC], p[KC], xa[KC], r[KC];
     // p starts from e: the stencil's own centre values (no second load)
-    stencil_chunk<T, KC>(in.g, in.E, ps.i, ps.j, ps.k0, a, p);
+    stencil_m<T, KC, MESH>(in.g, in.E, ps, a, p);
     // r is needed only for the next beta's products at the end: binary32
     // loads it there (the registers it frees give that kernel a sixth wave
     // per SIMD); FP64 loads it with the iterate (there a late load is
@@ -1524,7 +1639,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta(Table<T> tb, int in
 }
 
 // x = x_base + sum_{l = x_base_nu .. x_final_hi} beta_l p^l, into X[0].
-template <typename T, int KC>
+template <typename T, int KC, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_finalize_x(Table<T> tb)
 {
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
@@ -1533,7 +1648,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_finalize_x(Table<T> tb)
     const SolveState* st = in.st;
     const int lo = st->x_base_nu, hi = st->x_final_hi;
     if (st->x_base == 0 && hi < lo) return;
-    const StPos ps = st_pos(in, lb);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
     if (!ps.col_ok) return;
     const double* xb = in.X[st->x_base];
     double* xo = in.X[0];
@@ -1653,7 +1768,7 @@ __global__ void k_event_inject(Table<T> tb, const long long* idx, const unsigned
 }
 
 // <r, L p^nu> and <L p^nu, L p^nu> recomputed after a flip in r or L(p^nu).
-template <typename T>
+template <typename T, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
 {
     __shared__ double sh[4];
@@ -1661,7 +1776,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
     SolveState* st = in.st;
     if (!st->ev_ok) return;
     const int lb = blockIdx.x;
-    const StPos ps = st_pos(in, lb);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
     double an = 0.0, ad = 0.0;
     if (ps.col_ok) {
         const T* r = in.R[st->r_cur];
@@ -1703,13 +1818,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_finish_beta_dots(Table<T> tb)
 // parity entry points
 // ---------------------------------------------------------------------------
 
-template <int KC>
+template <int KC, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, const double* x, double* y)
 {
     const Inst<double>& in = tb.inst[0];
-    const StPos ps = st_pos(in, blockIdx.x);
+    const StPos ps = st_pos_m<MESH>(in, blockIdx.x, in.kc);
     double ax[KC];
-    stencil_chunk<double, KC>(in.g, x, ps.i, ps.j, ps.k0, ax);
+    stencil_m<double, KC, MESH>(in.g, x, ps, ax);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
         if (ps.col_ok && ps.k0 + kk < in.g.nz)
@@ -1772,10 +1887,28 @@ void Launch<T>::set_round(const Table<T>& tb, double tol2, long long max_steps, 
     hipLaunchKernelGGL(k_set_round<T>, dim3(tb.n), dim3(64), 0, s, tb, tol2, max_steps);
 }
 
+// A stencil-pass launch on the table's mesh (the octahedral mesh: FP64).
+#define FTGCR_MESH_LAUNCH(tb, LAUNCH0, LAUNCH1)                                   \
+    do {                                                                          \
+        if ((tb).mesh == FTGCR_MESH_OCTAHEDRAL) {                                 \
+            if constexpr (sizeof(T) == 8) {                                       \
+                constexpr int MESHV = FTGCR_MESH_OCTAHEDRAL;                      \
+                LAUNCH1;                                                          \
+            }                                                                     \
+        } else {                                                                  \
+            constexpr int MESHV = FTGCR_MESH_LATLON;                              \
+            LAUNCH0;                                                              \
+        }                                                                         \
+    } while (0)
+
 template <typename T>
 void Launch<T>::residual(const Table<T>& tb, int total, int kc, int store, int set_T, hipStream_t s)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_residual<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb, store));
+    FTGCR_MESH_LAUNCH(tb,
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_residual<T, KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb,
+                                               store)),
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_residual<T, KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb,
+                                               store)));
     hipLaunchKernelGGL(k_finish_residual<T>, dim3(tb.n), dim3(RED_THREADS), 0, s, tb, set_T);
 }
 
@@ -1834,8 +1967,11 @@ template <typename T>
 void Launch<T>::stencil_dots(const Table<T>& tb, int total, int kc, int spec, hipStream_t s, hipEvent_t e0,
                              hipEvent_t e1)
 {
-    FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_stencil_dots<T, KCV>), dim3(total), dim3(ST_THREADS), s, tb,
-                                           spec));
+    FTGCR_MESH_LAUNCH(tb,
+        FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_stencil_dots<T, KCV, MESHV>), dim3(total),
+                                               dim3(ST_THREADS), s, tb, spec)),
+        FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_stencil_dots<T, KCV, MESHV>), dim3(total),
+                                               dim3(ST_THREADS), s, tb, spec)));
 }
 
 template <typename T>
@@ -1849,17 +1985,26 @@ void Launch<T>::dir_update(const Table<T>& tb, int total, int kc, int init, bool
                            hipEvent_t e0, hipEvent_t e1)
 {
     if (nt_ap)
-        FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, true>), dim3(total), dim3(ST_THREADS),
-                                               s, tb, init))
+        FTGCR_MESH_LAUNCH(tb,
+            FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, true, MESHV>), dim3(total),
+                                                   dim3(ST_THREADS), s, tb, init)),
+            FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, true, MESHV>), dim3(total),
+                                                   dim3(ST_THREADS), s, tb, init)));
     else
-        FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, false>), dim3(total),
-                                               dim3(ST_THREADS), s, tb, init))
+        FTGCR_MESH_LAUNCH(tb,
+            FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, false, MESHV>), dim3(total),
+                                                   dim3(ST_THREADS), s, tb, init)),
+            FTGCR_KC_SWITCH(kc, FTGCR_TIMED_LAUNCH(e0, e1, (k_dir_update<T, KCV, false, MESHV>), dim3(total),
+                                                   dim3(ST_THREADS), s, tb, init)));
 }
 
 template <typename T>
 void Launch<T>::finalize_x(const Table<T>& tb, int total, int kc, hipStream_t s)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_finalize_x<T, KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb));
+    FTGCR_MESH_LAUNCH(tb,
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_finalize_x<T, KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb)),
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_finalize_x<T, KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s,
+                                               tb)));
 }
 
 template <typename T>
@@ -1884,7 +2029,8 @@ void Launch<T>::event_inject(const Table<T>& tb, int grid, const long long* idx,
 template <typename T>
 void Launch<T>::beta_dots(const Table<T>& tb, int total, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_beta_dots<T>, dim3(total), dim3(ST_THREADS), 0, s, tb);
+    FTGCR_MESH_LAUNCH(tb, hipLaunchKernelGGL((k_beta_dots<T, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb),
+                      hipLaunchKernelGGL((k_beta_dots<T, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb));
     hipLaunchKernelGGL(k_finish_beta_dots<T>, dim3(1), dim3(RED_THREADS), 0, s, tb);
 }
 
@@ -1897,7 +2043,12 @@ template <>
 void Launch<double>::debug_apply_A(const Table<double>& tb, int total, int kc, const double* in, double* out,
                                    hipStream_t s)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_debug_apply_A<KCV>), dim3(total), dim3(ST_THREADS), 0, s, tb, in, out));
+    using T = double;
+    FTGCR_MESH_LAUNCH(tb,
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_debug_apply_A<KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb,
+                                               in, out)),
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_debug_apply_A<KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb,
+                                               in, out)));
 }
 
 template <typename T>

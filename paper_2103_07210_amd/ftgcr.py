@@ -22,6 +22,7 @@ FP64, MIXED = 0, 1
 PRECOND_NONE, PRECOND_COLUMN = 0, 1
 CONVERGED, MAX_STEPS, STAGNATED, BREAKDOWN = 0, 1, 2, 3
 METHOD_GCR, METHOD_GMRES = 0, 1
+MESH_LATLON, MESH_OCTAHEDRAL = 0, 1
 KMAX = 16
 LOG_CAP = 256
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -41,7 +42,7 @@ class FtgcrError(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("nlon", ctypes.c_int32), ("nlat", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("shell_depth", ctypes.c_double)]
+                ("shell_depth", ctypes.c_double), ("mesh", ctypes.c_int32)]
 
 
 class Coeffs(ctypes.Structure):
@@ -158,7 +159,10 @@ def _check(rc: int, handle=None):
 
 
 def _grid(pb) -> Grid:
-    return Grid(pb.nx, pb.ny, pb.nz, pb.shell_depth)
+    """Lat-lon problems have nx, ny; octahedral ones N (their O_N)."""
+    if hasattr(pb, "N"):
+        return Grid(0, pb.N, pb.nz, pb.shell_depth, MESH_OCTAHEDRAL)
+    return Grid(pb.nx, pb.ny, pb.nz, pb.shell_depth, MESH_LATLON)
 
 
 def _coeffs(pb) -> Coeffs:

@@ -53,6 +53,34 @@ class Problem:
         return (self.nz, self.ny, self.nx)
 
 
+@dataclasses.dataclass(frozen=True)
+class OctProblem:
+    """The octahedral reduced Gaussian grid O_N of the paper's experiments
+    (Section 3, Table 1) with nz levels: 4N(N+9) points per level, fields
+    [nz][points]; coefficients as for Problem."""
+    N: int
+    nz: int
+    shell_depth: float = 1.0
+    hill_lon: float = math.pi / 2
+    hill_lat: float = math.pi / 6
+    hill_amp: float = 0.5
+    hill_width: float = 0.35
+    decay_z: float = 0.3
+    helmholtz: float = 1e-3
+
+    @property
+    def points(self) -> int:
+        return 4 * self.N * (self.N + 9)
+
+    @property
+    def n(self) -> int:
+        return self.points * self.nz
+
+    @property
+    def shape(self):
+        return (self.nz, self.points)
+
+
 @dataclasses.dataclass
 class FaultEvent:
     """XOR `bit` (or per-entry `bits`) into entries of one working vector
@@ -86,6 +114,10 @@ class FaultEvent:
 Plan = List[FaultEvent]
 
 # --- the five workload configurations ---------------------------------------
+
+# the paper's O160 with its 51 levels (Table 1) and a small octahedral case
+O160 = OctProblem(160, 51)
+O40 = OctProblem(40, 51)
 
 C1 = Problem(64, 32, 8)
 C2 = Problem(256, 128, 32)
