@@ -1142,3 +1142,48 @@ int orc_oct_solve(const orc_oct_problem* pb, const double* rhs, double* x, doubl
     oct_close(&q);
     return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Solves with a chosen preconditioner: the column one, or none (P = I).      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    latlon_ctx q;
+    int64_t n;
+} latlon_id_ctx;
+
+static void latlon_A_id(const void* c, const double* x, double* y)
+{
+    const latlon_id_ctx* q = (const latlon_id_ctx*)c;
+    orc_apply_A(q->q.pb, q->q.wx, q->q.wy, q->q.wz, x, y);
+}
+
+/* e = r: no preconditioner */
+static void identity_pinv(const void* c, const double* r, double* e)
+{
+    const latlon_id_ctx* q = (const latlon_id_ctx*)c;
+    copy_vec(q->n, r, e);
+}
+
+int orc_solve_pc(const orc_problem* pb, int32_t precond, int32_t method, const double* rhs, double* x,
+                 double tol, int32_t k, int64_t max_steps, int32_t ft,
+                 const orc_event* events, int32_t n_events, orc_stats* st,
+                 orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
+{
+    if (!pb || pb->nx < 3 || pb->ny < 1 || pb->nz < 1 || (precond != 0 && precond != 1)) return -1;
+    latlon_id_ctx c;
+    op_pair op;
+    if (latlon_open(pb, &c.q, &op) != 0) return -1;
+    c.n = op.n;
+    if (precond == 0) {
+        op.apply_A = latlon_A_id;
+        op.apply_pinv = identity_pinv;
+        op.ctx = &c;
+    }
+    const int rc = method == 1
+        ? gmres_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap)
+        : gcr_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap,
+                   NULL, NULL, 0);
+    latlon_close(&c.q);
+    return rc;
+}

@@ -149,6 +149,14 @@ int orc_gmres_solve(const orc_problem* pb, const double* rhs, double* x, double 
                     const orc_event* events, int32_t n_events, orc_stats* st,
                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
 
+/* FT-GCR(k) (method 0) or FT-GMRES(k) (method 1) on a lat-lon problem with
+ * the column preconditioner (precond 1) or none (precond 0: P = I);
+ * arguments and outcomes as for orc_solve. */
+int orc_solve_pc(const orc_problem* pb, int32_t precond, int32_t method, const double* rhs, double* x,
+                 double tol, int32_t k, int64_t max_steps, int32_t ft,
+                 const orc_event* events, int32_t n_events, orc_stats* st,
+                 orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
+
 /* Octahedral reduced Gaussian grid O_N (Section 3, Table 1): 2N rings of
  * 4i + 16 points (i = 1..N from either pole), 4N(N+9) points per level, at
  * the Gaussian latitudes, with the node-centred finite-volume operator on the

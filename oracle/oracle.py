@@ -105,6 +105,8 @@ def _load():
         lib.orc_solve_traced.restype = ctypes.c_int
         lib.orc_gmres_solve.argtypes = lib.orc_solve.argtypes
         lib.orc_gmres_solve.restype = ctypes.c_int
+        lib.orc_solve_pc.argtypes = [P, ctypes.c_int32, ctypes.c_int32] + lib.orc_solve.argtypes[1:]
+        lib.orc_solve_pc.restype = ctypes.c_int
         OP = ctypes.POINTER(_OctProblem)
         lib.orc_oct_cells.argtypes = [ctypes.c_int32]
         lib.orc_oct_cells.restype = ctypes.c_int64
@@ -332,13 +334,17 @@ class Oracle:
 
     def solve(self, rhs, x0=None, tol: float = 1e-10, k: int = 3, max_steps: int = 100000,
               ft: bool = True, plan: Optional[Sequence] = None, log_cap: int = 4096,
-              hist_cap: Optional[int] = None, trace: bool = False, method: str = "gcr"):
-        """Run FT-GCR(k) (method 'gcr') or FT-GMRES(k) ('gmres').  Returns
-        (x, stats dict, detection log, rr history).  With trace=True (GCR
-        only) the stats also hold the per-step orthogonality diagnostics
-        'cos_r_ap' and 'cos_ap' (see orc_solve_traced)."""
-        if method not in ("gcr", "gmres") or (trace and method != "gcr"):
-            raise ValueError("method is 'gcr' or 'gmres'; trace is for 'gcr'")
+              hist_cap: Optional[int] = None, trace: bool = False, method: str = "gcr",
+              precond: str = "column"):
+        """Run FT-GCR(k) (method 'gcr') or FT-GMRES(k) ('gmres') with the
+        column preconditioner or none (precond 'none': P = I).  Returns
+        (x, stats dict, detection log, rr history).  With trace=True (GCR,
+        column preconditioner) the stats also hold the per-step
+        orthogonality diagnostics 'cos_r_ap' and 'cos_ap' (see
+        orc_solve_traced)."""
+        if method not in ("gcr", "gmres") or precond not in ("column", "none") or \
+                (trace and (method != "gcr" or precond != "column")):
+            raise ValueError("method is 'gcr' or 'gmres', precond 'column' or 'none'; trace is for GCR")
         rhs = _vec(rhs, self.n)
         x = np.zeros(self.n) if x0 is None else _vec(x0, self.n).copy()
         plan = list(plan or [])
@@ -371,7 +377,12 @@ class Oracle:
         st = _Stats()
         cos_r_ap = np.zeros(max(1, hist_cap)) if trace else None
         cos_ap = np.zeros(max(1, hist_cap)) if trace else None
-        if method == "gmres":
+        if precond == "none":
+            rc = _load().orc_solve_pc(
+                ctypes.byref(self._c), 0, 1 if method == "gmres" else 0, _ptr(rhs), _ptr(x), float(tol), int(k),
+                int(max_steps), 1 if ft else 0, events, len(plan), ctypes.byref(st), log, int(log_cap),
+                _ptr(hist), int(hist_cap))
+        elif method == "gmres":
             rc = _load().orc_gmres_solve(
                 ctypes.byref(self._c), _ptr(rhs), _ptr(x), float(tol), int(k), int(max_steps),
                 1 if ft else 0, events, len(plan), ctypes.byref(st), log, int(log_cap),

@@ -221,3 +221,37 @@ def test_edge_cases(oracle_mod):
         o.solve(rhs, tol=1e-10, k=3, plan=[FaultEvent(1, "r", 64, idx=np.array([0]))])
     with pytest.raises(ValueError):
         o.solve(rhs, tol=1e-10, k=3, plan=[FaultEvent(1, "r", 1, idx=np.array([pb.n]))])
+
+
+def test_unpreconditioned_single_cycle_equals_gmres(oracle_mod):
+    """With P = I (no preconditioner) one long cycle of GCR equals GMRES on
+    A itself (scipy), and GMRES(k) the oracle's own GCR on the same cycle."""
+    pb = TINY[0]
+    o = oracle_mod.Oracle(pb)
+    n = pb.n
+    rhs = I.rhs(pb, 14).reshape(-1)
+    steps = 40
+    x, st, _, hist = o.solve(rhs, tol=1e-30, k=steps + 5, max_steps=steps, ft=False, precond="none")
+    _, sg, _, hg = o.solve(rhs, tol=1e-30, k=steps + 5, max_steps=steps, ft=False, precond="none", method="gmres")
+    m = o.dense_matrix()
+    res = []
+    gmres(m, rhs, x0=np.zeros(n), rtol=1e-300, atol=0.0, restart=steps, maxiter=1,
+          callback=lambda pr: res.append(pr), callback_type="pr_norm")
+    res = np.array(res[:steps])
+    gcr = np.sqrt(hist / st["rhs_norm2"])
+    keep = res > 1e-9
+    assert keep.sum() >= 15
+    np.testing.assert_allclose(gcr[: len(res)][keep], res[keep], rtol=1e-6)
+    np.testing.assert_allclose(np.sqrt(hg / st["rhs_norm2"])[: len(res)][keep], res[keep], rtol=1e-6)
+
+
+@pytest.mark.parametrize("method", ["gcr", "gmres"])
+def test_unpreconditioned_solution_matches_dense_lu(oracle_mod, method):
+    pb = TINY[1]
+    o = oracle_mod.Oracle(pb)
+    rhs = I.rhs(pb, 15).reshape(-1)
+    m = o.dense_matrix()
+    ref = np.linalg.solve(m, rhs)
+    x, st, _, _ = o.solve(rhs, tol=1e-12, k=8, precond="none", method=method, max_steps=200000)
+    assert st["status"] == oracle_mod.CONVERGED
+    assert np.linalg.norm(x.reshape(-1) - ref) / np.linalg.norm(ref) <= 2 * np.linalg.cond(m) * 1e-12
