@@ -15,8 +15,12 @@
  * and top) with c = 1 + hill_amp * h(lon, lat) * exp(-zeta / decay_z),
  * h = exp(-(gc / hill_width)^2) (gc: great-circle distance to the hill
  * centre), plus a shift: A = A0 + helmholtz * diag(A0).  The preconditioner
- * P is the vertical (column) tridiagonal part of A; the paper only states
- * that GCR is left-preconditioned for the anisotropy of the domain (Section 2).
+ * P is the vertical (column) tridiagonal part of A, or P = I; the paper only
+ * states that GCR is left-preconditioned for the anisotropy of the domain
+ * (Section 2).  The same operator is built on the octahedral reduced
+ * Gaussian grid O_N of the paper's experiments (Section 3, Table 1), and the
+ * fault layer is also offered on restarted GMRES(k), the other Krylov
+ * solver the method is meant to carry over to (abstract, Section 1).
  *
  * Conventions
  *  - Every field is a contiguous C-order array [nz][nlat][nlon] (longitude
@@ -52,6 +56,10 @@ typedef enum {
 } ftgcr_status;
 
 typedef enum { FTGCR_FP64 = 0, FTGCR_MIXED = 1 } ftgcr_precision;
+/* Preconditioner P of the left-preconditioned iteration (Section 2: the
+ * paper preconditions for the anisotropy of the domain without giving P):
+ * COLUMN is the vertical tridiagonal part of A (A's diagonal and vertical
+ * couplings), solved per column; NONE is P = I. */
 typedef enum { FTGCR_PRECOND_NONE = 0, FTGCR_PRECOND_COLUMN = 1 } ftgcr_precond;
 
 /* Solve outcomes (ftgcr_stats.status). */
@@ -206,33 +214,57 @@ typedef struct {
 
 typedef struct ftgcr_handle ftgcr_handle;
 
-/* Fill *opt with defaults: ft=1, poll_steps=16, max_steps=100000,
- * inner_tol=3e-5, max_refinements=20, inner_max_steps=5000, hist_cap=65536,
- * use_graphs=1, levels_per_block=0. */
+/* Fill *opt with defaults: ft=1 (the fault layer of Algorithm 1 on),
+ * method=GCR, poll_steps=16, max_steps=100000, inner_tol=3e-5,
+ * max_refinements=20, inner_max_steps=5000, hist_cap=65536, use_graphs=1,
+ * levels_per_block=0.  opt must not be NULL. */
 void ftgcr_default_options(ftgcr_options* opt);
 
-/* Create a solver for one grid and coefficient set on the current HIP device.
- * Builds the FP64 coefficient tables (hill at cell and face centres, vertical
- * decay, metric factors) and the device state.  kmax bounds k in later solves
- * (1 <= kmax <= FTGCR_KMAX).  hip_stream is a hipStream_t (NULL: default). */
+/* Create a solver for one grid and coefficient set on the current HIP device
+ * (the operator L of Eq. (1) discretised as described at the top; the
+ * preconditioner of Section 2).  Builds the FP64 coefficient tables (hill at
+ * cell and face centres, vertical decay, metric factors; on O_N the mesh's
+ * neighbour lists, face weights and control areas) and the device state.
+ *  grid, coeffs : host, read during the call.  nz <= 96.
+ *  precond      : FTGCR_PRECOND_COLUMN or FTGCR_PRECOND_NONE (P = I; the
+ *                 lat-lon mesh only).
+ *  precision    : FTGCR_FP64, or FTGCR_MIXED (lat-lon mesh only).
+ *  kmax         : bounds k in later solves (1 <= kmax <= FTGCR_KMAX).
+ *  hip_stream   : a hipStream_t (NULL: the default stream).
+ *  out          : receives the handle (NULL on failure); free with
+ *                 ftgcr_destroy.
+ * Returns E_INVALID for bad arguments, E_UNSUPPORTED for valid combinations
+ * that are not built, E_NOMEM / E_HIP on allocation or runtime failure;
+ * ftgcr_last_error(NULL) then holds the message. */
 ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs,
                           ftgcr_precond precond, ftgcr_precision precision,
                           int32_t kmax, void* hip_stream, ftgcr_handle** out);
 
+/* Replace the handle's options (read from host *opt during the call);
+ * E_INVALID, options unchanged, when a field is out of range (k-independent
+ * fields only: k is checked by each solve) or a method is asked for that the
+ * handle's mesh or precision does not build (FT-GMRES: FP64 lat-lon). */
 ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt);
+/* Copy the handle's options to host *opt. */
 ftgcr_status ftgcr_get_options(const ftgcr_handle* h, ftgcr_options* opt);
+/* Enqueue later work on hip_stream (a hipStream_t of the handle's device,
+ * NULL: the default stream). */
 ftgcr_status ftgcr_set_stream(ftgcr_handle* h, void* hip_stream);
 
 /* Device workspace the caller must provide (bytes), for the handle's kmax:
- * 2 (kmax+1) + 4 working vectors in the storage precision (directions p^l,
- * their images L(p^l), three residual buffers, e = P^{-1} r), one FP64 iterate
- * buffer, block partial sums and the residual history. */
+ * the working vectors of Algorithm 1 in the storage precision -- the
+ * directions p^l and their images L(p^l) with their backup copies (the
+ * saved state of Section 2), three residual buffers and e = P^{-1} r -- one
+ * FP64 iterate buffer, block partial sums and the residual history (for
+ * FT-GMRES the k+1 basis vectors, k preconditioned vectors and the
+ * backup).  0 when h is NULL. */
 size_t ftgcr_workspace_bytes(const ftgcr_handle* h);
 /* dev_ptr: device memory of at least ftgcr_workspace_bytes(h) bytes, 256-byte
  * aligned, owned by the caller and kept alive while the handle solves. */
 ftgcr_status ftgcr_set_workspace(ftgcr_handle* h, void* dev_ptr, size_t bytes);
 
-/* Solve A x = rhs (Eq. (1)) with FT-GCR(k), Algorithm 1.
+/* Solve A x = rhs (Eq. (1)) with FT-GCR(k), Algorithm 1 (with
+ * options.method = GMRES: FT-GMRES(k), the fault layer on restarted GMRES).
  *  rhs_dev : device, FP64, N entries (read only).
  *  x_dev   : device, FP64, N entries; in: initial guess phi^0, out: solution.
  *  tol     : FP64 handles stop when <r,r> <= tol^2 <R,R> on the recursive
@@ -266,8 +298,10 @@ ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev,
 ftgcr_status ftgcr_solve_noalloc(ftgcr_handle* h, const double* rhs_dev, double* x_dev, double tol, int32_t k,
                                  const ftgcr_fault_plan* plan, ftgcr_stats* stats);
 
-/* Solve n independent problems at once (an ensemble): every handle must be
- * FP64, have its own workspace and share the first handle's stream; their
+/* Solve n independent problems at once (an ensemble of the elliptic solves
+ * of Eq. (1), each with FT-GCR(k) of Algorithm 1): every handle must be FP64,
+ * lat-lon, GCR, with the same preconditioner, have its own workspace and
+ * share the first handle's stream; their
  * step kernels run as combined launches over all unfinished members, each
  * member keeping its own convergence and fault state on the device.
  * rhs[m], x[m], tol[m] as in ftgcr_solve; plans may be NULL (no faults) or an
@@ -277,7 +311,8 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n,
                                const double* tol, int32_t k,
                                const ftgcr_fault_plan* plans, ftgcr_stats* stats);
 
-/* Tiling autotune of a batch (the ensemble's launch shape): times `steps`
+/* Tiling autotune of a batch (the ensemble's launch shape; measurement of
+ * the solve of ftgcr_solve_batch, no change to its arithmetic): times `steps`
  * batched steps of these members (fault-free, from x = 0) at 2, 4 and 8
  * stencil levels per block (those not above the deepest member's nz), keeps
  * the fastest in hs[0]'s options.batch_levels_per_block and writes it to
@@ -288,7 +323,9 @@ ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n,
                                   const double* const* rhs, double* const* x_scratch,
                                   int32_t k, int32_t steps, int32_t* chosen);
 
-/* Autotuner of the stencil tiling (levels of a column per block): times
+/* Autotuner of the stencil tiling (levels of a column per block) of the
+ * operator application L(p) of Algorithm 1 (the results do not depend on
+ * the choice beyond the order of the block partial sums): times
  * `steps` steps of this problem for each candidate and keeps the fastest for
  * this handle (options.levels_per_block = 0) and for every later handle with
  * the same grid and precision in this process.  x_scratch_dev: FP64 device
@@ -296,7 +333,8 @@ ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n,
 ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_scratch_dev, int32_t k,
                             int32_t steps, int32_t* chosen);
 
-/* Per-kernel device time accumulated while options.profile_kernels != 0:
+/* Per-kernel device time (measurement of the step of Algorithm 1)
+ * accumulated while options.profile_kernels != 0:
  * one record per kernel of the step sequence (update_thomas, stencil_dots,
  * dir_update), each the sum of its launches' execution times (start and
  * stop events stamped by each dispatch)
@@ -308,8 +346,11 @@ typedef struct {
     double total_ms;
 } ftgcr_kernel_time;
 ftgcr_status ftgcr_kernel_times(const ftgcr_handle* h, ftgcr_kernel_time* out, int32_t cap, int32_t* n_out);
+/* Zero the accumulated kernel times. */
 ftgcr_status ftgcr_reset_kernel_times(ftgcr_handle* h);
 
+/* Free the handle and its device state (not the caller's workspace, which
+ * the caller frees after this call).  NULL is a no-op. */
 void ftgcr_destroy(ftgcr_handle* h);
 
 /* HBM bandwidth probe (measurement, no solver state): copies `bytes` from
@@ -326,8 +367,11 @@ ftgcr_status ftgcr_bw_probe(const void* src_dev, void* dst_dev, size_t bytes, in
  * is NULL).  Valid until the next call on the same handle. */
 const char* ftgcr_last_error(const ftgcr_handle* h);
 
-/* Parity entry points (FP64, device pointers of N entries, on the handle's
- * stream, synchronous): out = A in, and out = P^{-1} in. */
+/* Parity entry points (FP64, device pointers of N entries in the field
+ * layout above, caller-owned, not overlapping, on the handle's stream,
+ * synchronous): out = A in (the operator L of Eq. (1)), and
+ * out = P^{-1} in (the preconditioner of Section 2; a copy for P = I).
+ * Both run in FP64 whatever the handle's precision. */
 ftgcr_status ftgcr_debug_apply_A(ftgcr_handle* h, const double* in_dev, double* out_dev);
 ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, double* out_dev);
 

@@ -858,7 +858,8 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     h->nt_ap = nt_ap_hint(k, h->geo.n, (int)sizeof(T));
     HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh}, s};
+    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond},
+                  s};
     run.noalloc = staging != nullptr;
     const Table<T>& tb = run.tb;
     const bool mixed = h->precision == FTGCR_MIXED;
@@ -975,7 +976,7 @@ ftgcr_status gm_solve_impl(ftgcr_handle* h, const double* rhs, double* x, double
     HIP_TRY(h, hipStreamSynchronize(s));
     const GmInst* d = h->gm_inst;
     // geometry and the column grid of the two-lane FP64 column kernel
-    const Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1};
+    const Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond};
     const int nblk_col = (h->geo.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK;
     const int nst = h->nblk_st, kc = h->kc;
     GmState* hs = h->gm_host;
@@ -1156,7 +1157,7 @@ ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins
     sh.cols = pre[na];
     sh.sts = pre[2 * na + 1];
     sh.dirs = pre[3 * na + 2];
-    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na};
+    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na, FTGCR_MESH_LATLON, h0->precond};
     return FTGCR_OK;
 }
 
@@ -1243,7 +1244,10 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     Table<double> tb{};
     rc = upload_batch(h0, ins, members, B.inst, B.blk0, sh, tb);
     if (rc != FTGCR_OK) return rc;
-    auto single = [&](int m) { return Table<double>{B.all + m, hs[m]->blk0, hs[m]->blk0 + 2, hs[m]->blk0 + 4, 1}; };
+    auto single = [&](int m) {
+        return Table<double>{B.all + m, hs[m]->blk0, hs[m]->blk0 + 2, hs[m]->blk0 + 4, 1, FTGCR_MESH_LATLON,
+                             h0->precond};
+    };
 
     hipEvent_t e0 = h0->ev_start, e1 = h0->ev_stop;
     (void)hipEventRecord(e0, s);
@@ -1439,13 +1443,15 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
         return fail(nullptr, FTGCR_E_INVALID, "octahedral grid needs N = nlat in 1..4000 and nz >= 1");
     if (oct && precision != FTGCR_FP64)
         return fail(nullptr, FTGCR_E_UNSUPPORTED, "the octahedral mesh is built for FP64 handles");
+    if (oct && precond != FTGCR_PRECOND_COLUMN)
+        return fail(nullptr, FTGCR_E_UNSUPPORTED, "the octahedral mesh is built with the column preconditioner");
     if (!(grid->shell_depth > 0)) return fail(nullptr, FTGCR_E_INVALID, "shell_depth must be > 0");
     if (!(coeffs->hill_width > 0) || !(coeffs->decay_z > 0) || !(coeffs->hill_amp >= 0) || !(coeffs->helmholtz > 0))
         return fail(nullptr, FTGCR_E_INVALID, "coefficients need hill_width > 0, decay_z > 0, hill_amp >= 0, helmholtz > 0");
     if (kmax < 1 || kmax > FTGCR_KMAX) return fail(nullptr, FTGCR_E_INVALID, "kmax out of range");
     if (precision != FTGCR_FP64 && precision != FTGCR_MIXED) return fail(nullptr, FTGCR_E_INVALID, "bad precision");
-    if (precond != FTGCR_PRECOND_COLUMN)
-        return fail(nullptr, FTGCR_E_UNSUPPORTED, "only the column preconditioner is built");
+    if (precond != FTGCR_PRECOND_COLUMN && precond != FTGCR_PRECOND_NONE)
+        return fail(nullptr, FTGCR_E_INVALID, "precond must be FTGCR_PRECOND_COLUMN or FTGCR_PRECOND_NONE");
     if (thomas_depth(grid->nz) < 0) return fail(nullptr, FTGCR_E_UNSUPPORTED, "nz > 96 is not supported");
     const long long ncols = oct ? oct_points(grid->nlat) : (long long)grid->nlon * grid->nlat;
     if (ncols > (1LL << 30) || ncols * grid->nz > (1LL << 40)) return fail(nullptr, FTGCR_E_UNSUPPORTED, "grid too large");
@@ -1599,6 +1605,8 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
             return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves run FT-GCR (options.method of every member)");
         if (h->geo.mesh != FTGCR_MESH_LATLON)
             return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are built for the lat-lon mesh");
+        if (h->precond != hs[0]->precond)
+            return fail(hs[0], FTGCR_E_INVALID, "batch members with different preconditioners");
         if (!rhs[m] || !x[m]) return fail(hs[0], FTGCR_E_INVALID, "rhs or x is NULL");
         if (!(tol[m] > 0) || !std::isfinite(tol[m])) return fail(hs[0], FTGCR_E_INVALID, "tol must be finite and > 0");
         if (k < 1 || k > h->kmax) return fail(hs[0], FTGCR_E_INVALID, "k must be in [1, kmax] of every member");
@@ -1824,7 +1832,7 @@ ftgcr_status ftgcr_debug_apply_A(ftgcr_handle* h, const double* in_dev, double* 
     if (!h) return FTGCR_E_INVALID;
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
-    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh};
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond};
     Launch<double>::debug_apply_A(tb, h->nblk_st, h->kc, in_dev, out_dev, h->stream);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -1836,7 +1844,7 @@ ftgcr_status ftgcr_debug_apply_Pinv(ftgcr_handle* h, const double* in_dev, doubl
     if (!h) return FTGCR_E_INVALID;
     if (!in_dev || !out_dev) return fail(h, FTGCR_E_INVALID, "in or out is NULL");
     HIP_TRY(h, hipSetDevice(h->device));
-    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh};
+    Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond};
     // the FP64 two-lane kernel, whatever the handle's own column tiling
     Launch<double>::debug_pinv(tb, (h->geo.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK, h->H, in_dev, out_dev,
                                h->stream);

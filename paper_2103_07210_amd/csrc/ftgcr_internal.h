@@ -206,6 +206,7 @@ struct Table {
     const int* blk0_dir;     // n + 1 prefix sums (direction-pass grid)
     int n;
     int mesh = 0;            // every instance's mesh (FTGCR_MESH_*)
+    int precond = FTGCR_PRECOND_COLUMN;   // every instance's preconditioner
 };
 
 // Kernel launchers (kernels.hip).

@@ -1340,6 +1340,77 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas1(Table<T> tb)
     }
 }
 
+// No preconditioner (P = I): the column pass's update, stored r+ and norms,
+// with e = r+ (MODE_GM: v_j normalised and z_j = v_j; MODE_DEBUG: out = in).
+// It runs on the column grid (cpb columns per block, all their levels), so
+// the decision kernels read the same partial rows.
+template <typename T, int mode>
+__global__ __launch_bounds__(COL_THREADS) void k_update_copy(Table<T> tb, const T* dbg_in, T* dbg_out,
+                                                             const GmInst* gm, int cpb)
+{
+    __shared__ double sh[4];
+    const int m = find_inst(tb.blk0_col, tb.n, blockIdx.x);
+    const Inst<T>& in = tb.inst[m];
+    const int lb = blockIdx.x - tb.blk0_col[m];
+    SolveState* st = in.st;
+    if (mode == MODE_STEP || mode == MODE_INIT) {
+        if (st->status != RUNNING) return;
+        if (mode == MODE_STEP && st->d_cur == 0.0) return;   // the decision records the breakdown
+    }
+    if (mode == MODE_GM) {
+        if (gm->st->status != RUNNING || !gm->st->active) return;
+    }
+    const T* rin;
+    const T* ap = nullptr;
+    T* rout = nullptr;
+    T* eout;
+    double beta = 0.0, den = 1.0;
+    if (mode == MODE_DEBUG) {
+        rin = dbg_in;
+        eout = dbg_out;
+    } else if (mode == MODE_GM) {
+        const int jj = gm->st->j;
+        rin = (const T*)gm->U[jj];
+        rout = (T*)gm->U[jj];
+        eout = (T*)gm->Z[jj];
+        den = gm->st->den[jj];
+    } else {
+        rin = in.R[st->r_cur];
+        eout = in.E;
+        if (mode == MODE_STEP) {
+            ap = in.AP[st->slot[st->nu]];
+            rout = in.R[st->r_dst];
+            beta = -st->beta_num / st->d_cur;
+        }
+    }
+    const int ncols = in.g.ncols, nz = in.g.nz;
+    const long long plane = (long long)ncols;
+    const int c0 = lb * cpb;
+    const int cols = ncols - c0 < cpb ? ncols - c0 : cpb;
+    double acc_new = 0.0, acc_st = 0.0;
+    for (int t = threadIdx.x; t < cpb * nz; t += COL_THREADS) {
+        const int q = t % cpb, k = t / cpb;
+        if (q >= cols) continue;
+        const long long o = (long long)(c0 + q) + plane * k;
+        const double v = (mode == MODE_STEP) ? fma(beta, (double)ap[o], (double)rin[o])
+                         : (mode == MODE_GM) ? (double)rin[o] / den
+                                             : (double)rin[o];
+        const T sv = (T)v;
+        const double rp = (double)sv;
+        if (mode == MODE_STEP || mode == MODE_GM) rout[o] = sv;
+        eout[o] = sv;
+        acc_new = fma(v, v, acc_new);
+        acc_st = fma(rp, rp, acc_st);
+    }
+    if (mode == MODE_DEBUG || mode == MODE_GM) return;
+    const double sn = block_sum(acc_new, sh);
+    const double ss = block_sum(acc_st, sh);
+    if (threadIdx.x == 0) {
+        in.part[(long long)(0) * in.pstride + lb] = sn;
+        in.part[(long long)(1) * in.pstride + lb] = ss;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_finish_col(Table<T> tb, int mode)
 {
@@ -1916,6 +1987,16 @@ template <typename T>
 void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1)
 {
+    if (tb.precond == FTGCR_PRECOND_NONE) {
+        const int cpb = col_block_cols((int)sizeof(T), H);
+        if (mode == MODE_STEP)
+            FTGCR_TIMED_LAUNCH(e0, e1, (k_update_copy<T, MODE_STEP>), dim3(total), dim3(COL_THREADS), s, tb,
+                               (const T*)nullptr, (T*)nullptr, (const GmInst*)nullptr, cpb);
+        else
+            hipLaunchKernelGGL((k_update_copy<T, MODE_INIT>), dim3(total), dim3(COL_THREADS), 0, s, tb,
+                               (const T*)nullptr, (T*)nullptr, (const GmInst*)nullptr, cpb);
+        return;
+    }
     if constexpr (sizeof(T) == 4) {
         if (col_block_cols((int)sizeof(T), H) == COL_THREADS) {
             // one lane per column: NZ = 2H levels at most (H <= 32)
@@ -2060,6 +2141,11 @@ template <>
 void Launch<double>::debug_pinv(const Table<double>& tb, int total, int H, const double* in, double* out,
                                 hipStream_t s)
 {
+    if (tb.precond == FTGCR_PRECOND_NONE) {
+        hipLaunchKernelGGL((k_update_copy<double, MODE_DEBUG>), dim3(total), dim3(COL_THREADS), 0, s, tb, in, out,
+                           (const GmInst*)nullptr, COLS_PER_BLOCK);
+        return;
+    }
     FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_DEBUG>), dim3(total), dim3(COL_THREADS),
                                          0, s, tb, in, out, (const GmInst*)nullptr));
 }
@@ -2614,6 +2700,11 @@ void GmLaunch::restart(const GmInst* gi, hipStream_t s)
 
 void GmLaunch::precond(const Table<double>& tb, const GmInst* gi, int nblk_col, int H, hipStream_t s)
 {
+    if (tb.precond == FTGCR_PRECOND_NONE) {
+        hipLaunchKernelGGL((k_update_copy<double, MODE_GM>), dim3(nblk_col), dim3(COL_THREADS), 0, s, tb,
+                           (const double*)nullptr, (double*)nullptr, gi, COLS_PER_BLOCK);
+        return;
+    }
     FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_GM>), dim3(nblk_col), dim3(COL_THREADS),
                                          0, s, tb, (const double*)nullptr, (double*)nullptr, gi));
 }

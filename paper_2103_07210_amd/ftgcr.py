@@ -211,9 +211,12 @@ def _stats_out(st: Stats, log, hist) -> dict:
 
 class Solver:
     """One FT-GCR handle on the current device: grid, coefficients,
-    precision ('fp64' or 'mixed') and the largest k it will solve with."""
+    precision ('fp64' or 'mixed'), the largest k it will solve with and the
+    preconditioner ('column': the vertical tridiagonal part of A; 'none':
+    P = I)."""
 
-    def __init__(self, problem, precision: str = "fp64", kmax: int = 4, stream=None, **options):
+    def __init__(self, problem, precision: str = "fp64", kmax: int = 4, stream=None, precond: str = "column",
+                 **options):
         import torch
         lib = load()
         self.problem = problem
@@ -223,7 +226,8 @@ class Solver:
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         g, c = _grid(problem), _coeffs(problem)
-        _check(lib.ftgcr_create(ctypes.byref(g), ctypes.byref(c), PRECOND_COLUMN, self.precision, kmax,
+        self.precond = {"column": PRECOND_COLUMN, "none": PRECOND_NONE}[precond]
+        _check(lib.ftgcr_create(ctypes.byref(g), ctypes.byref(c), self.precond, self.precision, kmax,
                                 ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h)), None)
         self._h = h
         self._ws = None

@@ -65,8 +65,9 @@ def test_default_options_and_create_errors_without_gpu(lib):
                             ctypes.byref(h)) == ftgcr.E_UNSUPPORTED
     assert lib.ftgcr_create(ctypes.byref(ftgcr.Grid(8, 4, 4, 1.0)), ctypes.byref(c), 1, 0, 17, None,
                             ctypes.byref(h)) == ftgcr.E_INVALID
-    assert lib.ftgcr_create(ctypes.byref(ftgcr.Grid(8, 4, 4, 1.0)), ctypes.byref(c), 0, 0, 3, None,
-                            ctypes.byref(h)) == ftgcr.E_UNSUPPORTED
+    assert lib.ftgcr_create(ctypes.byref(ftgcr.Grid(8, 4, 4, 1.0)), ctypes.byref(c), 2, 0, 3, None,
+                            ctypes.byref(h)) == ftgcr.E_INVALID
+    assert b"precond" in lib.ftgcr_last_error(None)
     assert not h.value
 
 

@@ -1,0 +1,159 @@
+"""GPU parity of the solves without a preconditioner (P = I, precond
+'none') against the oracle's P = I path on the same seeded inputs, through
+the C ABI: e = P^-1 r is a copy of r, the rest of FT-GCR(k) / FT-GMRES(k) and
+the fault layer of Algorithm 1 are unchanged.
+
+Bars as for the preconditioned solves: identical decision lists, natural
+executed-step counts within +-1, x within 1e-10 relative at equal executed-
+step counts.  A is symmetric here, so with P = I every GCR(k) is the
+conjugate residual method and its step count does not depend on k (the
+oracle shows 620 steps for k = 1..8 on the 64 x 32 x 8 case); the oracle's
+counts do not move under 2e-16 perturbations of the right-hand side on the
+cases used (measured).  Without a preconditioner the late residual
+history is chaotic: under such perturbations the oracle's own squared
+residual norms move by up to 2e-2 relative once |r| < 1e-9 |R| and by at
+most 5e-8 above 1e-8 |R| (GCR, measured), and by at most 2e-5 for the GMRES
+case; the histories are compared within 1e-6 relative above 1e-16 |R|^2
+(GCR) and within 1e-3 above 1e-24 |R|^2 (GMRES)."""
+import numpy as np
+import pytest
+
+from paper_2103_07210_amd import inputs as I
+from paper_2103_07210_amd.inputs import FaultEvent, Problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ft():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2103_07210_amd import ftgcr
+    ftgcr.load()
+    return ftgcr
+
+
+def _decisions(log):
+    return [(d["step"], d["nu"], d["action"]) for d in log]
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    assert np.array_equal(np.isfinite(a), np.isfinite(b))
+    f = np.isfinite(b)
+    # scaled first: an undetected flip of p can leave entries near 1e300 in
+    # x (the recursion never reads x), whose plain 2-norm overflows
+    sc = np.abs(b[f]).max()
+    return float(np.linalg.norm((a[f] - b[f]) / sc) / np.linalg.norm(b[f] / sc))
+
+
+PB = Problem(64, 32, 8, hill_amp=0.7, hill_lon=1.1)
+
+
+def test_pinv_is_identity(ft):
+    _say("P = I apply")
+    s = ft.Solver(PB, kmax=2, precond="none")
+    x = np.random.default_rng(4).uniform(-1, 1, PB.n)
+    assert np.array_equal(s.apply_pinv(x).cpu().numpy().ravel(), x)
+    s.close()
+
+
+def _parity(ft, oracle_mod, pb, k, method="gcr", plan=None, tol=1e-10, rhs_seed=3):
+    rhs = I.rhs(pb, rhs_seed)
+    m = ft.METHOD_GMRES if method == "gmres" else ft.METHOD_GCR
+    s = ft.Solver(pb, kmax=max(k, 2), precond="none", method=m)
+    x, st = s.solve(rhs, tol=tol, k=k, plan=plan, hist_cap=100000)
+    s.close()
+    o = oracle_mod.Oracle(pb)
+    _, so, logo, _ = o.solve(rhs, tol=tol, k=k, plan=plan, method=method, precond="none")
+    assert _decisions(st["log"]) == _decisions(logo), (st["log"], logo)
+    assert st["status"] == so["status"]
+    assert abs(st["steps_executed"] - so["steps_executed"]) <= 1, (st["steps_executed"], so["steps_executed"])
+    assert st["events_applied"] == so["events_applied"]
+    xe, _, _, he = o.solve(rhs, tol=tol * 1e-3, k=k, plan=plan, method=method, precond="none",
+                           max_steps=st["steps_executed"])
+    err = _rel(x.cpu().numpy(), xe)
+    assert err <= 1e-10, err
+    n = min(len(he), len(st["hist"]))
+    keep = he[:n] > (1e-16 if method == "gcr" else 1e-24) * so["rhs_norm2"]
+    np.testing.assert_allclose(st["hist"][:n][keep], he[:n][keep], rtol=1e-6 if method == "gcr" else 1e-3)
+    _say(f"{method} k={k}: steps {st['steps_executed']} (oracle {so['steps_executed']}), "
+         f"decisions {_decisions(st['log'])}, x error {err:.1e}")
+    return st, so
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_gcr_matches_oracle(ft, oracle_mod, k):
+    _say("P = I gcr", k)
+    st, so = _parity(ft, oracle_mod, PB, k)
+    assert st["status"] == ft.CONVERGED
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_gcr_fault_decisions_match_oracle(ft, oracle_mod, case):
+    n = PB.n
+    plans = [
+        [FaultEvent(5, "r", 62, idx=np.array([1234]))],
+        [FaultEvent(7, "ap", 62, idx=np.arange(0, n, 97))],
+        [FaultEvent(6, "e", 62, idx=np.array([5, 600, 7000])), FaultEvent(9, "x", 61, idx=np.array([3]))],
+        [FaultEvent(12, "r", 52, start=100, count=n // 10), FaultEvent(13, "p", 62, idx=np.array([77]))],
+    ]
+    _say("P = I faults", case)
+    _parity(ft, oracle_mod, PB, 3, plan=plans[case])
+
+
+def test_gmres_matches_oracle(ft, oracle_mod):
+    _say("P = I gmres")
+    st, so = _parity(ft, oracle_mod, Problem(16, 8, 4, hill_amp=0.7, hill_lon=1.1), 12, method="gmres")
+    assert st["status"] == ft.CONVERGED
+
+
+def test_mixed_reaches_true_residual(ft, oracle_mod):
+    """binary32 vectors with e = r+ stored in binary32: the FP64 true
+    residual meets the tolerance (checked with the oracle's operator)."""
+    _say("P = I mixed")
+    rhs = I.rhs(PB, 21)
+    tol = 1e-8
+    s = ft.Solver(PB, "mixed", kmax=3, precond="none")
+    x, st = s.solve(rhs, tol=tol, k=3)
+    s.close()
+    assert st["status"] == ft.CONVERGED
+    o = oracle_mod.Oracle(PB)
+    xg = x.cpu().numpy()
+    true = o.true_residual(xg, rhs)
+    assert true <= tol * 1.001, true
+    xo, _, _, _ = o.solve(rhs, tol=1e-12, k=3, precond="none")
+    assert _rel(xg, xo) <= 2.1e3 * tol
+
+
+def test_batch_of_unpreconditioned_members(ft, oracle_mod):
+    """A batch of P = I members gives each member's own solve (decisions and
+    steps as the oracle's); members with different preconditioners are
+    rejected."""
+    pbs = [Problem(32, 16, 8, hill_amp=0.5), Problem(48, 24, 6)]
+    rhs = [I.rhs(pb, 7 + m) for m, pb in enumerate(pbs)]
+    plans = [[FaultEvent(4, "r", 62, idx=np.array([99]))], []]
+    solvers = [ft.Solver(pb, kmax=3, precond="none") for pb in pbs]
+    _say("P = I batch")
+    xs, sts = ft.solve_batch(solvers, rhs, k=3, plans=plans)
+    for m, pb in enumerate(pbs):
+        _, so, logo, _ = oracle_mod.Oracle(pb).solve(rhs[m], tol=1e-10, k=3, plan=plans[m], precond="none")
+        assert _decisions(sts[m]["log"]) == _decisions(logo), m
+        assert abs(sts[m]["steps_executed"] - so["steps_executed"]) <= 1
+    c = ft.Solver(pbs[0], kmax=3)
+    with pytest.raises(ft.FtgcrError):
+        ft.solve_batch([c, solvers[0]], [rhs[0], rhs[0]], k=3)
+    for s in solvers + [c]:
+        s.close()
+
+
+def test_octahedral_needs_the_column_preconditioner(ft):
+    with pytest.raises(ft.FtgcrError):
+        ft.Solver(I.OctProblem(4, 5), kmax=3, precond="none")

@@ -255,3 +255,39 @@ def test_unpreconditioned_solution_matches_dense_lu(oracle_mod, method):
     x, st, _, _ = o.solve(rhs, tol=1e-12, k=8, precond="none", method=method, max_steps=200000)
     assert st["status"] == oracle_mod.CONVERGED
     assert np.linalg.norm(x.reshape(-1) - ref) / np.linalg.norm(ref) <= 2 * np.linalg.cond(m) * 1e-12
+
+
+def test_unpreconditioned_gcr_is_conjugate_residual(oracle_mod):
+    """A is symmetric, so with P = I the coefficients against all but the
+    latest direction vanish and GCR(k) for every k is the conjugate residual
+    method: the residual histories for k = 1, 2, 5 agree while well above
+    rounding, and match a textbook conjugate-residual recurrence on the dense
+    matrix."""
+    pb = TINY[1]
+    o = oracle_mod.Oracle(pb)
+    m = o.dense_matrix()
+    assert np.allclose(m, m.T, rtol=0, atol=1e-14 * np.abs(m).max())
+    rhs = I.rhs(pb, 16).reshape(-1)
+    steps = 60
+    hs = [o.solve(rhs, tol=1e-30, k=k, max_steps=steps, ft=False, precond="none")[3] for k in (1, 2, 5)]
+    # conjugate residual: x = 0, r = p = b; alpha = <r, A r> / <A p, A p>;
+    # beta = <r+, A r+> / <r, A r>; A p carried along
+    r = rhs.copy()
+    p = r.copy()
+    ar = m @ r
+    ap = ar.copy()
+    ref = []
+    for _ in range(steps):
+        rar = r @ ar
+        alpha = rar / (ap @ ap)
+        r = r - alpha * ap
+        ref.append(r @ r)
+        ar = m @ r
+        beta = (r @ ar) / rar
+        p = r + beta * p
+        ap = ar + beta * ap
+    ref = np.array(ref)
+    keep = ref > 1e-16 * (rhs @ rhs)
+    assert keep.sum() >= 20
+    for h in hs:
+        np.testing.assert_allclose(h[:steps][keep], ref[keep], rtol=1e-7)
