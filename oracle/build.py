@@ -1,7 +1,8 @@
 """Build the FT-GCR CPU oracle (test infrastructure only).
 
 The oracle is plain C compiled by gcc with no fast-math and no FP contraction,
-so every operation is the IEEE-754 binary64 operation written in the source.
+so every operation is the IEEE-754 binary64 operation written in the source;
+OpenMP splits only loops whose results do not depend on the thread count.
 """
 import os
 import subprocess
@@ -12,7 +13,7 @@ LIB = os.path.join(HERE, "libftgcr_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11",
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c11", "-fopenmp",
            "-Wall", "-Wextra", "-fPIC", "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

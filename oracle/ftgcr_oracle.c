@@ -1,18 +1,55 @@
 /*
  * FT-GCR reference oracle -- TEST INFRASTRUCTURE ONLY (see ftgcr_oracle.h).
  *
- * Plain, serial FP64 C, written to be checked by eye against the paper
- * (Gillard & Benacchio, arXiv 2103.07210) and the frozen operator readings.
- * No blocking, fusion or reordering: every step of Algorithm 1 is a separate
+ * Plain FP64 C, written to be checked by eye against the paper (Gillard &
+ * Benacchio, arXiv 2103.07210) and the frozen operator readings.  No
+ * blocking, fusion or reordering: every step of Algorithm 1 is a separate
  * whole-vector pass, every inner product is a left-to-right sum.
  *
- * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fPIC -shared -lm
+ * Threads (OpenMP builds, orc_set_threads): only the face weights and the
+ * operator and preconditioner applications are split, by whole planes or
+ * columns whose
+ * outputs are disjoint and computed with the same operations in the same
+ * order as in the serial loop, so every result is bitwise the serial one;
+ * inner products and vector updates stay single serial loops.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -fPIC -shared -lm
  */
 #include "ftgcr_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_OMP(x) _Pragma(#x)
+#else
+#define ORC_OMP(x)
+#endif
+
+/* fields smaller than this are never split across threads */
+#define ORC_PAR_MIN 65536
+
+int orc_set_threads(int32_t n)
+{
+    if (n < 1) return -1;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+    return 0;
+#else
+    return n == 1 ? 0 : -1;
+#endif
+}
+
+int32_t orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -58,9 +95,12 @@ void orc_face_weights(const orc_problem* pb, double* wx, double* wy, double* wz)
     const double dlon = 2.0 * M_PI / nx;
     const double dlat = M_PI / ny;
     const double dz = pb->shell_depth / nz;
+    const int par = (int64_t)nx * ny * nz >= ORC_PAR_MIN;
+    (void)par;
 
     /* Longitude faces: flux c * (1/cos(lat)) d/dlon over a face of area
      * dlat*dz, difference over dlon. */
+    ORC_OMP(omp parallel for schedule(static) if(par))
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -70,6 +110,7 @@ void orc_face_weights(const orc_problem* pb, double* wx, double* wy, double* wz)
 
     /* Latitude faces: flux c d/dlat over a face of area cos(lat_face)*dlon*dz;
      * zero flux through the two polar faces. */
+    ORC_OMP(omp parallel for schedule(static) if(par))
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -84,6 +125,7 @@ void orc_face_weights(const orc_problem* pb, double* wx, double* wy, double* wz)
 
     /* Vertical faces: flux c d/dz over a face of area cos(lat)*dlon*dlat;
      * zero flux through bottom and top. */
+    ORC_OMP(omp parallel for schedule(static) if(par))
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -124,6 +166,9 @@ void orc_apply_A(const orc_problem* pb, const double* wx, const double* wy,
 {
     const int nx = pb->nx, ny = pb->ny, nz = pb->nz;
     const int64_t plane = (int64_t)nx * ny;
+    const int par = plane * nz >= ORC_PAR_MIN;
+    (void)par;
+    ORC_OMP(omp parallel for schedule(static) if(par))
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -148,8 +193,13 @@ void orc_apply_pinv(const orc_problem* pb, const double* wx, const double* wy,
 {
     const int nx = pb->nx, ny = pb->ny, nz = pb->nz;
     const int64_t plane = (int64_t)nx * ny;
+    const int par = plane * nz >= ORC_PAR_MIN;
+    (void)par;
+    ORC_OMP(omp parallel if(par))
+    {
     double* gam = (double*)malloc(sizeof(double) * nz);
     double* del = (double*)malloc(sizeof(double) * nz);
+    ORC_OMP(omp for schedule(static))
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             /* Rows of the column system: a_k e_{k-1} + b_k e_k + u_k e_{k+1} = r_k,
@@ -177,6 +227,7 @@ void orc_apply_pinv(const orc_problem* pb, const double* wx, const double* wy,
         }
     free(gam);
     free(del);
+    }
 }
 
 double orc_dot(int64_t n, const double* a, const double* b)
@@ -1004,7 +1055,6 @@ typedef struct {
     oct_mesh m;
     double* d;
     double* wzb;
-    double* off;
 } oct_ctx;
 
 static void oct_A(const void* cx, const double* x, double* y)
@@ -1014,10 +1064,15 @@ static void oct_A(const void* cx, const double* x, double* y)
     const orc_oct_problem* pb = m->pb;
     const int64_t nc = m->ncell;
     const double dz = pb->shell_depth / pb->nz;
+    const int par = nc * pb->nz >= ORC_PAR_MIN;
+    (void)par;
+    ORC_OMP(omp parallel if(par))
+    {
+    double* off = (double*)malloc(sizeof(double) * (size_t)nc);
+    ORC_OMP(omp for schedule(static))
     for (int k = 0; k < pb->nz; ++k) {
         const double gk = exp(-((k + 0.5) / pb->nz) / pb->decay_z);
         const double* xk = x + nc * k;
-        double* off = q->off;
         for (int64_t c = 0; c < nc; ++c) off[c] = 0.0;
         for (int64_t e = 0; e < m->nedge; ++e) {
             const double w = (1.0 + pb->hill_amp * m->eh[e] * gk) * dz * m->ew[e];
@@ -1031,6 +1086,8 @@ static void oct_A(const void* cx, const double* x, double* y)
             y[c + nc * k] = q->d[c + nc * k] * xk[c] - o;
         }
     }
+    free(off);
+    }
 }
 
 static void oct_pinv(const void* cx, const double* r, double* e)
@@ -1038,8 +1095,13 @@ static void oct_pinv(const void* cx, const double* r, double* e)
     const oct_ctx* q = (const oct_ctx*)cx;
     const int64_t nc = q->m.ncell;
     const int nz = q->m.pb->nz;
+    const int par = nc * nz >= ORC_PAR_MIN;
+    (void)par;
+    ORC_OMP(omp parallel if(par))
+    {
     double* gam = (double*)malloc(sizeof(double) * nz);
     double* del = (double*)malloc(sizeof(double) * nz);
+    ORC_OMP(omp for schedule(static))
     for (int64_t c = 0; c < nc; ++c) {
         /* a_k e_{k-1} + b_k e_k + u_k e_{k+1} = r_k: b the diagonal of A, a and u
          * minus the vertical face weights */
@@ -1062,6 +1124,7 @@ static void oct_pinv(const void* cx, const double* r, double* e)
     }
     free(gam);
     free(del);
+    }
 }
 
 static void oct_close(oct_ctx* q)
@@ -1069,7 +1132,6 @@ static void oct_close(oct_ctx* q)
     oct_mesh_free(&q->m);
     free(q->d);
     free(q->wzb);
-    free(q->off);
 }
 
 static int oct_open(const orc_oct_problem* pb, oct_ctx* q, op_pair* op)
@@ -1080,8 +1142,7 @@ static int oct_open(const orc_oct_problem* pb, oct_ctx* q, op_pair* op)
     const int64_t nc = q->m.ncell;
     q->d = (double*)malloc(sizeof(double) * (size_t)(nc * pb->nz));
     q->wzb = (double*)malloc(sizeof(double) * (size_t)(nc * (pb->nz + 1)));
-    q->off = (double*)malloc(sizeof(double) * (size_t)nc);
-    if (!q->d || !q->wzb || !q->off) {
+    if (!q->d || !q->wzb) {
         oct_close(q);
         return -1;
     }

@@ -1,5 +1,6 @@
 /*
- * FT-GCR reference oracle (plain C, FP64, serial).
+ * FT-GCR reference oracle (plain C, FP64; serial, or threaded with bitwise
+ * identical results).
  *
  * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library; it is
  * not part of the product path.  Only the test suite, the smoke check and the
@@ -65,6 +66,13 @@ void orc_apply_A(const orc_problem* pb, const double* wx, const double* wy,
 /* e = P^{-1} r, P = vertical tridiagonal part of A (one Thomas solve per column). */
 void orc_apply_pinv(const orc_problem* pb, const double* wx, const double* wy,
                     const double* wz, const double* r, double* e);
+
+/* Threads for the operator and preconditioner applications (OpenMP builds;
+ * results are bitwise independent of the count).  orc_set_threads returns 0,
+ * or -1 for n < 1 (or n > 1 in a build without OpenMP); orc_threads gives
+ * the count in use. */
+int orc_set_threads(int32_t n);
+int32_t orc_threads(void);
 
 /* Plain left-to-right FP64 inner product over n entries. */
 double orc_dot(int64_t n, const double* a, const double* b);

@@ -124,8 +124,23 @@ def _load():
                                       ctypes.c_int32, ctypes.POINTER(_Event), ctypes.c_int32, ctypes.POINTER(_Stats),
                                       ctypes.POINTER(_Detect), ctypes.c_int32, dp, ctypes.c_int64]
         lib.orc_oct_solve.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int32]
+        lib.orc_set_threads.restype = ctypes.c_int
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int32
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads for the operator and preconditioner applications; every
+    result is bitwise independent of the count."""
+    if _load().orc_set_threads(int(n)) != 0:
+        raise ValueError("thread count must be >= 1")
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
 
 
 def _problem(pb) -> _Problem:
