@@ -4,6 +4,7 @@ summaries the paper reports (Section 3, Tables 2-3).
   python -m paper_2103_07210_amd.campaign [--count 200] [--grid 256,128,32] [--k 4]
   python -m paper_2103_07210_amd.campaign --model paper [--prob 0.02]
          [--loss 4e-6,4e-4,2e-3,0.01,0.05,0.2] [--procs 36] [--count 100] [--k 5]
+         [--bits uniform|finite]
 
 The default model runs the seeded single-event campaign (one event per
 solve: step U{1..20}, vector x / r / p / A p, one entry, 1% of entries or a
@@ -151,6 +152,8 @@ def main():
     ap.add_argument("--loss", default="4e-6,4e-4,2e-3,0.01,0.05,0.2")
     ap.add_argument("--procs", type=int, default=36)
     ap.add_argument("--cap", type=float, default=4.0, help="paper model: step cap as a multiple of the fault-free count")
+    ap.add_argument("--bits", choices=("uniform", "finite"), default="uniform",
+                    help="paper model: which bits a flip may hit (all 64, or all but the top exponent bit)")
     args = ap.parse_args()
     pb = I.Problem(*[int(v) for v in args.grid.split(",")])
     import torch
@@ -163,12 +166,12 @@ def main():
         print(json.dumps(summary), flush=True)
         return
     for loss in [float(v) for v in args.loss.split(",")]:
-        plans = I.paper_plans(pb, args.count, prob=args.prob, data_loss=loss, procs=args.procs)
+        plans = I.paper_plans(pb, args.count, prob=args.prob, data_loss=loss, procs=args.procs, bits=args.bits)
         records, _, st_clean = run(pb, plans, k=args.k, tol=args.tol, rhs_seed=I.SEEDS["c2_rhs"],
                                    cap_factor=args.cap)
         summary = summarize_paper(records, st_clean["steps_executed"], st_clean["cycles"])
         summary.update({"grid": [pb.nx, pb.ny, pb.nz], "k": args.k, "prob": args.prob,
-                        "data_loss_percent": 100.0 * loss, "procs": args.procs})
+                        "data_loss_percent": 100.0 * loss, "procs": args.procs, "bits": args.bits})
         print(json.dumps(summary), flush=True)
 
 

@@ -190,17 +190,29 @@ def process_entries(problem: Problem, procs: int, rank: int) -> np.ndarray:
     return (cols[None, :] + ncols * np.arange(problem.nz, dtype=np.int64)[:, None]).ravel()
 
 
+# The two readings of which bit a flip hits (the paper does not say):
+# "uniform" draws it from all 64 bits of the binary64 pattern; "finite"
+# leaves out bit 62, the top exponent bit, whose flip takes a value in
+# [1, 2) to Inf or NaN and a value below 1 in magnitude to one above 2^1023
+# (whose square overflows), so that the corrupted entries stay finite and
+# their squares mostly so.
+BIT_READINGS = {"uniform": tuple(range(64)), "finite": tuple(range(62)) + (63,)}
+
+
 def paper_plans(problem: Problem, count: int, prob: float = 0.02, data_loss: float = 0.01,
                 procs: int = 36, max_events: int = 10, horizon: int = 1000, seed0: int = SEEDS["paper_plan0"],
-                bit_max: int = 63) -> List[Plan]:
+                bit_max: int = 63, bits: str = "") -> List[Plan]:
     """The paper's fault model (Section 3), one plan per run: after the
     preconditioner of every executed step a fault event happens with
     probability `prob`, at most `max_events` per run; an event hits one
     process drawn at random (one of `procs` bands of whole columns) and
-    flips one random bit U{0..bit_max} in each of ceil(data_loss * N)
-    distinct entries of that process' share of e = P^-1(r) (all of its
-    entries when the share is smaller).  Steps are drawn up to `horizon`;
-    events past the end of a run are not applied."""
+    flips one random bit in each of ceil(data_loss * N) distinct entries of
+    that process' share of e = P^-1(r) (all of its entries when the share is
+    smaller): U{0..bit_max}, or uniform over BIT_READINGS[bits] when `bits`
+    names a reading (the same random draws, mapped onto that set).  Steps
+    are drawn up to `horizon`; events past the end of a run are not
+    applied."""
+    choices = np.array(BIT_READINGS[bits] if bits else range(bit_max + 1), dtype=np.uint8)
     plans = []
     n = problem.n
     cnt = max(1, int(math.ceil(data_loss * n)))
@@ -211,8 +223,8 @@ def paper_plans(problem: Problem, count: int, prob: float = 0.02, data_loss: flo
         for step in hits.tolist():
             own = process_entries(problem, procs, int(rng.integers(0, procs)))
             idx = own if cnt >= own.size else np.sort(rng.choice(own, cnt, replace=False))
-            bits = rng.integers(0, bit_max + 1, idx.size).astype(np.uint8)
-            plan.append(FaultEvent(step=int(step), vec=VEC_E, bit=0, idx=idx.astype(np.int64), bits=bits))
+            flip = choices[rng.integers(0, choices.size, idx.size)]
+            plan.append(FaultEvent(step=int(step), vec=VEC_E, bit=0, idx=idx.astype(np.int64), bits=flip))
         plans.append(plan)
     return plans
 

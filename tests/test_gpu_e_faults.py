@@ -98,18 +98,20 @@ def test_e_event_at_the_last_allowed_step(ft, oracle_mod):
     assert _rel(x.cpu().numpy(), xo) <= 1e-12
 
 
-def test_paper_campaign_slice_matches_oracle(ft, oracle_mod):
+@pytest.mark.parametrize("bits", ["uniform", "finite"])
+def test_paper_campaign_slice_matches_oracle(ft, oracle_mod, bits):
     """The paper's fault model (Bernoulli per step, several events per run,
-    random bits in a process' share of e) on a small grid: per run the same
-    decisions and applied events as the oracle."""
+    random bits in a process' share of e) on a small grid, under both
+    readings of the flipped bit (any of 64, or all but the top exponent
+    bit): per run the same decisions and applied events as the oracle."""
     pb = Problem(64, 32, 8, hill_amp=0.7)
     rhs = I.rhs(pb, 2)
     o = oracle_mod.Oracle(pb)
     s = ft.Solver(pb, kmax=4)
-    plans = I.paper_plans(pb, 10, prob=0.08, data_loss=0.01, procs=8, horizon=120, seed0=7000)
+    plans = I.paper_plans(pb, 10, prob=0.08, data_loss=0.01, procs=8, horizon=120, seed0=7000, bits=bits)
     assert sum(len(p) for p in plans) > 10
     for m, plan in enumerate(plans):
-        _say("paper plan", m, [(e.step, e.count) for e in plan])
+        _say("paper plan", bits, m, [(e.step, e.count) for e in plan])
         x, st = s.solve(rhs, tol=1e-10, k=4, plan=plan)
         xo, so, logo, _ = o.solve(rhs, tol=1e-10, k=4, plan=plan)
         assert _decisions(st["log"]) == _decisions(logo), (m, st["log"], logo)

@@ -112,3 +112,17 @@ def test_paper_plans_shape():
             assert cols.max() - cols.min() < share // pb.nz + 1
     big = I.paper_plans(pb, 5, prob=0.5, data_loss=0.2, procs=8, horizon=20)
     assert all(ev.count == share for plan in big for ev in plan)
+    # the readings of the flipped bit: "uniform" is the U{0..63} stream
+    # itself; "finite" draws the same steps and entries and never bit 62
+    uni = I.paper_plans(pb, 20, prob=0.05, data_loss=0.01, procs=8, horizon=200, bits="uniform")
+    fin = I.paper_plans(pb, 20, prob=0.05, data_loss=0.01, procs=8, horizon=200, bits="finite")
+    ref = I.paper_plans(pb, 20, prob=0.05, data_loss=0.01, procs=8, horizon=200)
+    seen = np.zeros(64, dtype=bool)
+    for pu, pf, pr in zip(uni, fin, ref):
+        assert [e.step for e in pu] == [e.step for e in pf] == [e.step for e in pr]
+        for eu, ef, er in zip(pu, pf, pr):
+            assert np.array_equal(eu.bits, er.bits)
+            assert np.array_equal(eu.idx, ef.idx)
+            assert not np.any(ef.bits == 62)
+            seen[ef.bits] = True
+    assert seen.sum() == 63 and not seen[62]
