@@ -858,7 +858,9 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
     h->nt_ap = nt_ap_hint(k, h->geo.n, (int)sizeof(T));
     HIP_TRY(h, hipMemcpyAsync(h->inst, &in, sizeof in, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    Runner<T> run{h, Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond},
+    Runner<T> run{h,
+                  Table<T>{(const Inst<T>*)h->inst, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond,
+                           full_columns(h->geo.ncols, h->geo.nz, h->H) ? 1 : 0},
                   s};
     run.noalloc = staging != nullptr;
     const Table<T>& tb = run.tb;
@@ -1140,13 +1142,15 @@ struct BatchShape {
 // Upload the members' instance records and block prefixes into `inst` /
 // `blk0` (device, capacity for members.size()).
 ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins, const std::vector<int>& members,
-                          Inst<double>* inst, int* blk0, BatchShape& sh, Table<double>& tb)
+                          int H, Inst<double>* inst, int* blk0, BatchShape& sh, Table<double>& tb)
 {
     const int na = (int)members.size();
     std::vector<Inst<double>> act(na);
     std::vector<int> pre(3 * (na + 1), 0);
+    bool full = true;
     for (int q = 0; q < na; ++q) {
         act[q] = ins[members[q]];
+        full = full && full_columns(act[q].g.ncols, act[q].g.nz, H);
         pre[q + 1] = pre[q] + act[q].nblk_col;
         pre[na + 1 + q + 1] = pre[na + 1 + q] + act[q].nblk_st;
         pre[2 * (na + 1) + q + 1] = pre[2 * (na + 1) + q] + act[q].nblk_dir;
@@ -1157,7 +1161,8 @@ ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins
     sh.cols = pre[na];
     sh.sts = pre[2 * na + 1];
     sh.dirs = pre[3 * na + 2];
-    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na, FTGCR_MESH_LATLON, h0->precond};
+    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na, FTGCR_MESH_LATLON, h0->precond,
+                       full ? 1 : 0};
     return FTGCR_OK;
 }
 
@@ -1238,11 +1243,11 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
     // kernels
     BatchShape sh_all;
     Table<double> tb_all{};
-    rc = upload_batch(h0, ins, members, B.all, B.blk0_all, sh_all, tb_all);
+    rc = upload_batch(h0, ins, members, H, B.all, B.blk0_all, sh_all, tb_all);
     if (rc != FTGCR_OK) return rc;
     BatchShape sh;
     Table<double> tb{};
-    rc = upload_batch(h0, ins, members, B.inst, B.blk0, sh, tb);
+    rc = upload_batch(h0, ins, members, H, B.inst, B.blk0, sh, tb);
     if (rc != FTGCR_OK) return rc;
     auto single = [&](int m) {
         return Table<double>{B.all + m, hs[m]->blk0, hs[m]->blk0 + 2, hs[m]->blk0 + 4, 1, FTGCR_MESH_LATLON,
@@ -1340,7 +1345,7 @@ ftgcr_status solve_batch_impl(ftgcr_handle* const* hs, int n, const double* cons
         if (still.empty()) break;
         if (8 * done_blocks >= sh.sts) {
             members.swap(still);
-            rc = upload_batch(h0, ins, members, B.inst, B.blk0, sh, tb);
+            rc = upload_batch(h0, ins, members, H, B.inst, B.blk0, sh, tb);
             if (rc != FTGCR_OK) return rc;
         }
         if (launched > max_cap + chunk + 16) return fail(h0, FTGCR_E_HIP, "batched step loop did not terminate");

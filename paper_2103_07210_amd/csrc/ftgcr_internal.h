@@ -207,7 +207,18 @@ struct Table {
     int n;
     int mesh = 0;            // every instance's mesh (FTGCR_MESH_*)
     int precond = FTGCR_PRECOND_COLUMN;   // every instance's preconditioner
+    // 1: every instance's columns fill the two-lane column grid exactly
+    // (nz = 2H levels, a whole number of 128-column blocks), so every lane
+    // of the column pass owns every row it touches
+    int full = 0;
 };
+
+// Whether a problem of ncols columns and nz levels fills the two-lane column
+// grid exactly (Table::full).
+inline bool full_columns(long long ncols, int nz, int H)
+{
+    return nz == 2 * H && ncols % COLS_PER_BLOCK == 0;
+}
 
 // Kernel launchers (kernels.hip).
 template <typename T> struct Launch {

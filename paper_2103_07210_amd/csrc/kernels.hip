@@ -967,9 +967,8 @@ __device__ void decide_beta(SolveState* st, double num, double dn, int init)
 // MODE_GM (FT-GMRES, FP64): the current Arnoldi vector U[j] is divided by
 // den[j] (normalised, written back in place) and z_j = P^{-1} v_j goes to
 // Z[j]; no norms.
-template <typename T, int H, int mode>
-__global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, const T* dbg_in, T* dbg_out,
-                                                                const GmInst* gm)
+template <typename T, int H, int mode, bool FULL>
+__device__ __forceinline__ void update_thomas_body(Table<T> tb, const T* dbg_in, T* dbg_out, const GmInst* gm)
 {
     // The column solve runs in the storage precision: FP64 for FP64 solves;
     // binary32 for the mixed form, where e = P^{-1} r only has to be a fixed
@@ -979,6 +978,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     __shared__ double sh[4];
     __shared__ CT s_gc[2 * H];
     __shared__ CT s_gf[2 * H + 1];
+    // Half columns longer than 32 levels: the multipliers of the first LH
+    // rows (the last ones the back-substitution reads) wait in LDS, the rest
+    // in registers, so that the kernel fits two waves per SIMD (all 48
+    // levels in registers take about 370 registers in FP64: one wave)
+    constexpr int LH = H > 32 ? (sizeof(CT) == 8 ? 19 : 16) : 0;
+    constexpr int RH = H - LH;
+    __shared__ CT s_stk[LH > 0 ? LH : 1][2][COL_THREADS];
     const int m = find_inst(tb.blk0_col, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_col[m];
@@ -1071,7 +1077,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
     constexpr int NCH = H / CH;
     static_assert(H % CH == 0, "chunks must tile the half column");
     T bufr[2][CH], bufa[2][CH];
-    CT de[H], ga[H];
+    CT de[RH], ga[RH];
     double acc_new = 0.0, acc_st = 0.0;
     CT carry_g = 0, carry_d = 0;
     CT mm = 1, ff = 0, uu = 0;   // meeting row of the lower lane
@@ -1120,7 +1126,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
             const T sv = (T)v;
             const double rp = (double)sv;
             const CT rc = (CT)sv;
-            if (mine && valid) {
+            // When the columns fill the grid exactly (FULL), every lane owns
+            // every row it touches and stores r+ unguarded: behind a guard
+            // the compiler moves all rows' eliminations after all the
+            // stores, holding every row's values at once
+            if constexpr (FULL) {
+                if (mode == MODE_STEP) *rw = sv;
+                acc_new = fma(v, v, acc_new);
+                acc_st = fma(rp, rp, acc_st);
+            } else if (mine && valid) {
                 if (mode == MODE_STEP || mode == MODE_GM) *rw = sv;
                 acc_new = fma(v, v, acc_new);
                 acc_st = fma(rp, rp, acc_st);
@@ -1158,8 +1172,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
                 carry_g = meet ? carry_g : g_new;
                 carry_d = meet ? carry_d : d_new;
             }
-            ga[q] = g_new;
-            de[q] = d_new;
+            if (q < LH) {
+                s_stk[q < LH ? q : 0][0][threadIdx.x] = g_new;
+                s_stk[q < LH ? q : 0][1][threadIdx.x] = d_new;
+            } else {
+                ga[q - LH] = g_new;
+                de[q - LH] = d_new;
+            }
         }
     }
     // meeting row: the lower lane gets (zeta_h, eps_h) from its upper partner
@@ -1181,7 +1200,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
 #pragma unroll
     for (int q = H - 1; q >= 0; --q) {
         if (q < nback) {
-            xv = de[q] - ga[q] * xv;
+            CT gq, dq;
+            if (q < LH) {
+                gq = s_stk[q < LH ? q : 0][0][threadIdx.x];
+                dq = s_stk[q < LH ? q : 0][1][threadIdx.x];
+            } else {
+                gq = ga[q - LH];
+                dq = de[q - LH];
+            }
+            xv = dq - gq * xv;
             if (valid) *ep = (T)xv;
             ep += estep;
         }
@@ -1193,6 +1220,27 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, cons
         part[(long long)(0) * pstride + lb] = sn;
         part[(long long)(1) * pstride + lb] = ss;
     }
+}
+
+template <typename T, int H, int mode>
+__global__ __launch_bounds__(COL_THREADS) void k_update_thomas(Table<T> tb, const T* dbg_in, T* dbg_out)
+{
+    update_thomas_body<T, H, mode, false>(tb, dbg_in, dbg_out, nullptr);
+}
+
+// The step pass on columns that fill the grid exactly, held to two waves
+// per SIMD (its unguarded stores keep the long columns within 256 registers)
+template <typename T, int H>
+__global__ __launch_bounds__(COL_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_update_thomas_full(
+    Table<T> tb)
+{
+    update_thomas_body<T, H, MODE_STEP, true>(tb, nullptr, nullptr, nullptr);
+}
+
+template <int H>
+__global__ __launch_bounds__(COL_THREADS) void k_update_thomas_gm(Table<double> tb, const GmInst* gm)
+{
+    update_thomas_body<double, H, MODE_GM, false>(tb, nullptr, nullptr, gm);
 }
 
 // The binary32 column pass with one lane per column (256 columns per
@@ -2017,13 +2065,15 @@ void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hi
             return;
         }
     }
-    if (mode == MODE_STEP)
+    if (mode == MODE_STEP && tb.full)
+        FTGCR_H_SWITCH(H, FTGCR_TIMED_LAUNCH(e0, e1, (k_update_thomas_full<T, HV>), dim3(total), dim3(COL_THREADS),
+                                             s, tb))
+    else if (mode == MODE_STEP)
         FTGCR_H_SWITCH(H, FTGCR_TIMED_LAUNCH(e0, e1, (k_update_thomas<T, HV, MODE_STEP>), dim3(total),
-                                             dim3(COL_THREADS), s, tb, (const T*)nullptr, (T*)nullptr,
-                                             (const GmInst*)nullptr))
+                                             dim3(COL_THREADS), s, tb, (const T*)nullptr, (T*)nullptr))
     else
         FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<T, HV, MODE_INIT>), dim3(total), dim3(COL_THREADS), 0,
-                                             s, tb, (const T*)nullptr, (T*)nullptr, (const GmInst*)nullptr))
+                                             s, tb, (const T*)nullptr, (T*)nullptr))
 }
 
 template <typename T>
@@ -2147,7 +2197,7 @@ void Launch<double>::debug_pinv(const Table<double>& tb, int total, int H, const
         return;
     }
     FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_DEBUG>), dim3(total), dim3(COL_THREADS),
-                                         0, s, tb, in, out, (const GmInst*)nullptr));
+                                         0, s, tb, in, out));
 }
 
 // Status and step count of every instance into a small device array (one
@@ -2705,8 +2755,7 @@ void GmLaunch::precond(const Table<double>& tb, const GmInst* gi, int nblk_col, 
                            (const double*)nullptr, (double*)nullptr, gi, COLS_PER_BLOCK);
         return;
     }
-    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas<double, HV, MODE_GM>), dim3(nblk_col), dim3(COL_THREADS),
-                                         0, s, tb, (const double*)nullptr, (double*)nullptr, gi));
+    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas_gm<HV>), dim3(nblk_col), dim3(COL_THREADS), 0, s, tb, gi));
 }
 
 void GmLaunch::stencil(const GmInst* gi, int nblk, int kc, int dots, hipStream_t s)
