@@ -323,6 +323,16 @@ def main():
         _, bst = ftgcr.solve_batch(solvers, erhs, tols=[1e-10] * 64, k=3, plans=plans)
         torch.cuda.synchronize()
         batched_ms = (time.perf_counter() - t1) * 1e3
+        # the same batch with every chunk of steps launched directly (no
+        # graph replay), for the graph's share
+        solvers[0].set_options(use_graphs=0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, bst_d = ftgcr.solve_batch(solvers, erhs, tols=[1e-10] * 64, k=3, plans=plans)
+        torch.cuda.synchronize()
+        direct_ms = (time.perf_counter() - t1) * 1e3
+        solvers[0].set_options(use_graphs=1)
+        same_steps = [b["steps_executed"] for b in bst] == [b["steps_executed"] for b in bst_d]
         t1 = time.perf_counter()
         for sv, r, pl in zip(solvers, erhs, plans):
             sv.solve(r, tol=1e-10, k=3, plan=pl)
@@ -334,13 +344,16 @@ def main():
         # steps of the faulty members counted as executed) over the batched time
         ens_bytes = sum(solve_bytes(b["steps_executed"], 3, mb.problem.n, 8) for b, mb in zip(bst, members))
         ensemble = {"members": 64, "points": points, "k": 3, "tol": 1e-10, "levels_per_block": batch_kc,
-                    "batched_ms": batched_ms, "sequential_ms": seq_ms,
+                    "batched_ms": batched_ms, "batched_direct_ms": direct_ms,
+                    "graph_speedup": direct_ms / batched_ms, "graph_same_steps": same_steps,
+                    "sequential_ms": seq_ms,
                     "member_steps_total": steps_all, "member_steps_per_s_batched": steps_all / batched_ms * 1e3,
                     "all_converged": all(b["status"] == 0 for b in bst),
                     "alg_bytes": ens_bytes, "alg_gbs": ens_bytes / (batched_ms * 1e-3) / 1e9,
                     "frac": ens_bytes / (batched_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                     "detections": sum(b["detections"] for b in bst)}
-        print(f"[bench] ensemble: batched {batched_ms:.1f} ms, one by one {seq_ms:.1f} ms", flush=True)
+        print(f"[bench] ensemble: batched {batched_ms:.1f} ms (direct launches {direct_ms:.1f} ms), "
+              f"one by one {seq_ms:.1f} ms", flush=True)
         for sv in solvers:
             sv.close()
 

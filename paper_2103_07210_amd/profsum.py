@@ -102,6 +102,16 @@ def pmc(fetch_dir, write_dir, grid, cmd):
     traffic = (f_dir * sf + w_dir * sw) * 1024.0
     print(f"traffic_bytes_per_launch: {traffic:.0f}")
     print("\nThe copy of 1 GiB reads and writes 1 GiB; its counters give the scale from counter KiB to bytes.")
+    print("\nEvery FP64 step kernel, scaled bytes per launch (launches that moved more than 1 MiB):\n")
+    print("| kernel | launches | fetch MB | write MB | total MB |")
+    print("|---|---|---|---|---|")
+    for key in ("k_update_thomas_full<double", "k_update_thomas<double", "k_stencil_dots<double",
+                "k_dir_update<double"):
+        fk, n1 = avg_big(pick(fetch, key))
+        wk, n2 = avg_big(pick(write, key))
+        if n1 and n2:
+            fb, wb = fk * sf * 1024.0, wk * sw * 1024.0
+            print(f"| `{key}` | {min(n1, n2)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
 
 
 def read_traffic(path):
