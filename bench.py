@@ -99,6 +99,24 @@ def solve_bytes(steps, k, n, s, rounds=1, residual_passes=1, design=False):
     return total
 
 
+def gmres_solve_bytes(steps, cycles, k, n, s=8):
+    """Algorithmic bytes of a fault-free FT-GMRES(k) solve (classical
+    Gram-Schmidt, each phase's operands read once): step j of a cycle reads
+    v_j and writes z_j = P^-1 v_j (2 sweeps), forms w = A z_j with the
+    <w, v_i>, i <= j (reads z_j and v_0..v_j, writes w: j + 3), and
+    orthogonalises and normalises (reads w and v_0..v_j, writes v_{j+1}:
+    j + 3): 2j + 8 sweeps; a cycle of m steps adds the correction (reads x and
+    z_0..z_{m-1}, writes x: m + 2) and the explicit residual (reads x and R,
+    writes s: 3)."""
+    total = 0
+    left = steps
+    for _ in range(cycles):
+        m = min(k, left)
+        total += sum(2 * j + 8 for j in range(m)) + m + 5
+        left -= m
+    return total * s * n
+
+
 def step_frac(steps, k, n, s, ms, rounds=1, residual_passes=1):
     """Whole-solve rate on the algorithmic bytes against the HBM peak, and
     the design's bytes over them."""
@@ -153,6 +171,8 @@ def main():
                     help="short run for counter passes: one FP64 solve and the 1 GiB copy probe only")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member batched ensemble timing")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024x512x96 solves")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the octahedral O160 x 51 and FT-GMRES(16) timings")
     ap.add_argument("--grid", default="512,256,64",
                     help="with --profile-run: the grid of the profiled FP64 solve (nlon,nlat,nz)")
     args = ap.parse_args()
@@ -161,6 +181,7 @@ def main():
         ap.error("--grid is for --profile-run only; the benchmark workload is 512x256x64")
     if args.profile_run:
         args.steps, args.warmup, args.no_cpu, args.mixed_steps, args.no_ensemble, args.no_large = 1, 0, True, 0, True, True
+        args.no_extra = True
     if args.gpus != 1:
         print(json.dumps({"error": "the FT-GCR library runs on one GPU; sharding across GPUs (horizontal "
                                    "blocks of whole columns) is not implemented; run with --gpus 1"}))
@@ -382,6 +403,73 @@ def main():
             print(f"[bench] {name}: {ms_s:.2f} ms, {sts['steps_executed']} steps", flush=True)
             ss.close()
 
+    # the paper's octahedral mesh O160 with 51 levels (Table 1; 5.5 M points):
+    # FT-GCR(5) as in the paper's runs, FP64 to 1e-8, fault-free and with a
+    # 10% block of r flipped at step 10; and FT-GMRES(16) on 512 x 256 x 64
+    extra = None
+    if not args.no_extra:
+        extra = {}
+        po = I.O160
+        rhs_o = torch.from_numpy(I.rhs(po, I.SEEDS["c3_rhs"])).cuda()
+        so = ftgcr.Solver(po, "fp64", kmax=5, poll_steps=32)
+        kco = so.autotune(rhs_o, k=5, steps=12)
+        x_o = torch.zeros_like(rhs_o)
+        so.solve(rhs_o, x_o, tol=TOL, k=5)
+        runs_o = []
+        for _ in range(3):
+            x_o.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, sto = so.solve(rhs_o, x_o, tol=TOL, k=5)
+            torch.cuda.synchronize()
+            runs_o.append((time.perf_counter() - t1) * 1e3)
+        ms_o = float(np.median(runs_o))
+        so.set_options(profile_kernels=1)
+        so.reset_kernel_times()
+        x_o.zero_()
+        so.solve(rhs_o, x_o, tol=TOL, k=5)
+        kto = so.kernel_times()
+        so.set_options(profile_kernels=0)
+        plan_o = I.block_plan(po, step=10, vec="r", fraction=0.1, bit=62, seed=I.SEEDS["c5_plan"])
+        x_o.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sfo = so.solve(rhs_o, x_o, tol=TOL, k=5, plan=plan_o)
+        torch.cuda.synchronize()
+        ms_fo = (time.perf_counter() - t1) * 1e3
+        so.close()
+        fr = step_frac(sto["steps_executed"], 5, po.n, 8, ms_o)
+        extra["octahedral_O160x51"] = {
+            "points": po.n, "k": 5, "tol": TOL, "levels_per_block": kco, "ms": ms_o,
+            "steps": sto["steps_executed"], "us_per_step": ms_o * 1e3 / sto["steps_executed"],
+            "rel_res_true": sto["rel_res_true"], "alg_gbs": fr["alg_gbs"], "frac": fr["frac"],
+            "kernels_us": {q: v[1] / v[0] * 1e3 for q, v in kto.items() if v[0]},
+            "fault_10pct_r_bit62": {"ms": ms_fo, "steps": sfo["steps_executed"], "detections": sfo["detections"],
+                                    "steps_wasted": sfo["steps_wasted"], "rel_res_true": sfo["rel_res_true"]}}
+        print(f"[bench] O160x51 FT-GCR(5): {ms_o:.1f} ms, {sto['steps_executed']} steps, frac {fr['frac']:.3f}; "
+              f"10% r block: {ms_fo:.1f} ms, {sfo['detections']} detections", flush=True)
+        kg = 16
+        sg = ftgcr.Solver(pb, "fp64", kmax=kg, poll_steps=32, method=ftgcr.METHOD_GMRES, levels_per_block=kc64)
+        xg = torch.zeros_like(rhs)
+        sg.solve(rhs, xg, tol=TOL, k=kg)
+        runs_g = []
+        for _ in range(3):
+            xg.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, stg = sg.solve(rhs, xg, tol=TOL, k=kg)
+            torch.cuda.synchronize()
+            runs_g.append((time.perf_counter() - t1) * 1e3)
+        sg.close()
+        ms_g = float(np.median(runs_g))
+        gb = gmres_solve_bytes(stg["steps_executed"], stg["cycles"], kg, n)
+        extra["gmres_512x256x64"] = {
+            "k": kg, "tol": TOL, "ms": ms_g, "steps": stg["steps_executed"], "cycles": stg["cycles"],
+            "us_per_step": ms_g * 1e3 / stg["steps_executed"], "rel_res_true": stg["rel_res_true"],
+            "alg_bytes": gb, "alg_gbs": gb / (ms_g * 1e-3) / 1e9, "frac": gb / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        print(f"[bench] FT-GMRES(16) 512x256x64: {ms_g:.1f} ms, {stg['steps_executed']} steps, "
+              f"{stg['cycles']} cycles", flush=True)
+
     # the 1024 x 512 x 96 problem (one GPU's share of an 8-GPU run at
     # 8x the columns): FP64 and mixed, fault-free and with a 10% contiguous
     # block of r flipped (exponent MSB) at step 10
@@ -452,6 +540,7 @@ def main():
         "kernels": kernels,
         "ensemble_64": ensemble,
         "large_1024x512x96": large,
+        "extra": extra,
         "small_configs": small,
         "copy_probe_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

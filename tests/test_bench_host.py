@@ -69,3 +69,15 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_gmres_bytes_model():
+    """FT-GMRES(k): 2j + 8 sweeps for step j of a cycle, plus m + 5 per cycle
+    of m steps: k^2 + 8k + 5 sweeps for a full cycle."""
+    import bench
+    assert bench.gmres_solve_bytes(16, 1, 16, 1, 1) == 16 * 16 + 8 * 16 + 5
+    assert bench.gmres_solve_bytes(4, 1, 4, 1, 1) == 8 + 10 + 12 + 14 + 4 + 5
+    # two full cycles and a cut one of 3 steps, FP64 on 100 points
+    full = 16 * 16 + 8 * 16 + 5
+    cut = (8 + 10 + 12) + 3 + 5
+    assert bench.gmres_solve_bytes(35, 3, 16, 100) == (2 * full + cut) * 8 * 100
