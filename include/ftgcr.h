@@ -243,7 +243,7 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs,
 /* Replace the handle's options (read from host *opt during the call);
  * E_INVALID, options unchanged, when a field is out of range (k-independent
  * fields only: k is checked by each solve) or a method is asked for that the
- * handle's mesh or precision does not build (FT-GMRES: FP64 lat-lon). */
+ * handle's precision does not build (FT-GMRES: FP64 handles, either mesh). */
 ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt);
 /* Copy the handle's options to host *opt. */
 ftgcr_status ftgcr_get_options(const ftgcr_handle* h, ftgcr_options* opt);

@@ -1005,12 +1005,12 @@ ftgcr_status gm_solve_impl(ftgcr_handle* h, const double* rhs, double* x, double
             ap = ap || ev->vec == FTGCR_V_AP;
         }
         if (ap) {
-            G::stencil(d, nst, kc, 0, s);
+            G::stencil(d, nst, kc, 0, h->geo.mesh, s);
             for (const DevEvent* ev : at)
                 if (ev->vec == FTGCR_V_AP) inject(*ev, t);
             G::dots(d, nst, kc, s);
         } else {
-            G::stencil(d, nst, kc, 1, s);
+            G::stencil(d, nst, kc, 1, h->geo.mesh, s);
         }
         G::finish_h(d, s);
         G::orth(d, nst, kc, s);
@@ -1023,7 +1023,7 @@ ftgcr_status gm_solve_impl(ftgcr_handle* h, const double* rhs, double* x, double
     const long long guard = 4 * (h->opt.max_steps + 16) + 64;
     for (long long iter = 0;; ++iter) {
         if (iter > guard) return fail(h, FTGCR_E_HIP, "GMRES cycle loop did not terminate");
-        G::residual(d, nst, kc, s);
+        G::residual(d, nst, kc, h->geo.mesh, s);
         G::restart(d, s);
         rc = read_head();
         if (rc != FTGCR_OK) return rc;
@@ -1514,8 +1514,6 @@ ftgcr_status ftgcr_set_options(ftgcr_handle* h, const ftgcr_options* opt)
         return fail(h, FTGCR_E_INVALID, "invalid options");
     if (opt->method == FTGCR_METHOD_GMRES && h->precision != FTGCR_FP64)
         return fail(h, FTGCR_E_UNSUPPORTED, "FT-GMRES is built for FP64 handles");
-    if (opt->method == FTGCR_METHOD_GMRES && h->geo.mesh != FTGCR_MESH_LATLON)
-        return fail(h, FTGCR_E_UNSUPPORTED, "FT-GMRES is built for the lat-lon mesh");
     h->opt = *opt;
     set_tiling(h);
     if (h->graph) {

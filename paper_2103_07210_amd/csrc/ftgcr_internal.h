@@ -258,11 +258,11 @@ template <typename T> struct Launch {
 // for the column pass.
 struct GmLaunch {
     static void init(const GmInst* gi, int k, int ft, long long max_steps, double tol2, hipStream_t s);
-    static void residual(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
+    static void residual(const GmInst* gi, int nblk_st, int kc, int mesh, hipStream_t s);
     static void restart(const GmInst* gi, hipStream_t s);
     static void precond(const Table<double>& tb, const GmInst* gi, int nblk_col, int H, hipStream_t s);
     // dots = 0: store A z_j only (the dots follow a fault event on it)
-    static void stencil(const GmInst* gi, int nblk_st, int kc, int dots, hipStream_t s);
+    static void stencil(const GmInst* gi, int nblk_st, int kc, int dots, int mesh, hipStream_t s);
     static void dots(const GmInst* gi, int nblk_st, int kc, hipStream_t s);
     static void finish_h(const GmInst* gi, hipStream_t s);
     static void orth(const GmInst* gi, int nblk_st, int kc, hipStream_t s);

@@ -2244,6 +2244,15 @@ template struct Launch<float>;
 __device__ __forceinline__ StPos gm_pos(const GmInst& in, int lb)
 {
     StPos p;
+    if (in.g.mesh == FTGCR_MESH_OCTAHEDRAL) {   // ST_THREADS consecutive points per block
+        const int bxo = lb % in.tx;
+        const int i = bxo * ST_THREADS + threadIdx.x;
+        p.col_ok = i < in.g.nx;
+        p.i = p.col_ok ? i : in.g.nx - 1;
+        p.j = 0;
+        p.k0 = (lb / in.tx) * in.kc;
+        return p;
+    }
     const int bx = lb % in.tx;
     const int t = lb / in.tx;
     const int by = t % in.ty;
@@ -2289,7 +2298,7 @@ __global__ void k_gm_init(const GmInst* gi, int k, int ft, long long max_steps, 
 }
 
 // s = R - A x into U[0]; partials of <R, R> (row 0) and <s, s> (row 1).
-template <int KC>
+template <int KC, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_gm_residual(const GmInst* gi)
 {
     __shared__ double sh[4];
@@ -2301,7 +2310,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_gm_residual(const GmInst* gi)
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double ax[KC], b[KC];
-    stencil_chunk<double, KC>(in.g, in.X[st->x_cur], ps.i, ps.j, ps.k0, ax);
+    stencil_m<double, KC, MESH>(in.g, in.X[st->x_cur], ps, ax);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
@@ -2440,7 +2449,7 @@ __device__ __forceinline__ void gm_dots(const GmInst& in, const StPos& ps, const
 }
 
 // w = A z_j into W; with DOTS also the partials of <w, v_i>.
-template <int KC, int DOTS>
+template <int KC, int DOTS, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_gm_stencil(const GmInst* gi)
 {
     const GmInst& in = *gi;
@@ -2452,7 +2461,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_gm_stencil(const GmInst* gi)
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double w[KC];
-    stencil_chunk<double, KC>(in.g, in.Z[j], ps.i, ps.j, ps.k0, w);
+    stencil_m<double, KC, MESH>(in.g, in.Z[j], ps, w);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const bool ok = ps.col_ok && ps.k0 + kk < nz;
@@ -2738,9 +2747,14 @@ void GmLaunch::init(const GmInst* gi, int k, int ft, long long max_steps, double
     hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, gi, k, ft, max_steps, tol2);
 }
 
-void GmLaunch::residual(const GmInst* gi, int nblk, int kc, hipStream_t s)
+void GmLaunch::residual(const GmInst* gi, int nblk, int kc, int mesh, hipStream_t s)
 {
-    FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_residual<KCV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi));
+    if (mesh == FTGCR_MESH_OCTAHEDRAL)
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_residual<KCV, FTGCR_MESH_OCTAHEDRAL>), dim3(nblk),
+                                               dim3(ST_THREADS), 0, s, gi))
+    else
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_residual<KCV, FTGCR_MESH_LATLON>), dim3(nblk),
+                                               dim3(ST_THREADS), 0, s, gi))
 }
 
 void GmLaunch::restart(const GmInst* gi, hipStream_t s)
@@ -2758,12 +2772,19 @@ void GmLaunch::precond(const Table<double>& tb, const GmInst* gi, int nblk_col, 
     FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas_gm<HV>), dim3(nblk_col), dim3(COL_THREADS), 0, s, tb, gi));
 }
 
-void GmLaunch::stencil(const GmInst* gi, int nblk, int kc, int dots, hipStream_t s)
+void GmLaunch::stencil(const GmInst* gi, int nblk, int kc, int dots, int mesh, hipStream_t s)
 {
-    if (dots)
-        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_stencil<KCV, 1>), dim3(nblk), dim3(ST_THREADS), 0, s, gi))
-    else
-        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_stencil<KCV, 0>), dim3(nblk), dim3(ST_THREADS), 0, s, gi))
+#define FTGCR_GM_STENCIL(MV)                                                                                  \
+    if (dots)                                                                                                 \
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_stencil<KCV, 1, MV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi)) \
+    else                                                                                                      \
+        FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_gm_stencil<KCV, 0, MV>), dim3(nblk), dim3(ST_THREADS), 0, s, gi))
+    if (mesh == FTGCR_MESH_OCTAHEDRAL) {
+        FTGCR_GM_STENCIL(FTGCR_MESH_OCTAHEDRAL)
+    } else {
+        FTGCR_GM_STENCIL(FTGCR_MESH_LATLON)
+    }
+#undef FTGCR_GM_STENCIL
 }
 
 void GmLaunch::dots(const GmInst* gi, int nblk, int kc, hipStream_t s)

@@ -9,7 +9,9 @@ solvers on the same seeded inputs:
   step counts within +-1, x within 1e-10 at equal step counts;
 * a full solve at O160 x 51 reaching 1e-8 on the true residual evaluated
   with the oracle's operator, a 10% block of r flipped at step 10 detected
-  at that step.
+  at that step;
+* FT-GMRES(k) on O_N against the oracle's FT-GMRES on the same mesh,
+  fault-free and with faults.
 """
 import numpy as np
 import pytest
@@ -138,3 +140,52 @@ def test_o160_51_levels_full_solve(ft, oracle_mod):
     assert true <= 1.01e-8, true
     _say(f"O160x51: {st['steps_executed']} steps, {st['detections']} detections, {st['time_ms']:.1f} ms, "
          f"true residual {true:.2e}")
+
+
+def _gm_parity(ft, oracle_mod, pb, k, plan=None, tol=1e-10):
+    """FT-GMRES(k) on O_N against the oracle's (same bars as on the lat-lon
+    mesh; the cases are Krylov sizes at which the oracle's own step count
+    does not move under 2e-16 perturbations of the right-hand side)."""
+    rhs = np.random.default_rng(3).uniform(-1.0, 1.0, pb.n)
+    s = ft.Solver(pb, kmax=k, method=ft.METHOD_GMRES)
+    x, st = s.solve(rhs, tol=tol, k=k, plan=plan, hist_cap=100000)
+    s.close()
+    o = oracle_mod.OctOracle(pb)
+    _, so, logo, _ = o.solve(rhs, tol=tol, k=k, plan=plan, method="gmres")
+    assert _decisions(st["log"]) == _decisions(logo), (st["log"], logo)
+    assert st["status"] == so["status"] == ft.CONVERGED
+    assert abs(st["steps_executed"] - so["steps_executed"]) <= 1, (st["steps_executed"], so["steps_executed"])
+    assert st["events_applied"] == so["events_applied"]
+    xe, _, _, he = o.solve(rhs, tol=tol * 1e-3, k=k, plan=plan, method="gmres", max_steps=st["steps_executed"])
+    err = _rel(x.cpu().numpy(), xe)
+    assert err <= 1e-10, err
+    n = min(len(he), len(st["hist"]))
+    keep = he[:n] > 1e-24 * so["rhs_norm2"]
+    np.testing.assert_allclose(st["hist"][:n][keep], he[:n][keep], rtol=1e-2)
+    _say(f"gmres O{pb.N}x{pb.nz} k={k}: steps {st['steps_executed']} (oracle {so['steps_executed']}), "
+         f"decisions {_decisions(st['log'])}, x error {err:.1e}")
+    return st
+
+
+@pytest.mark.parametrize("case", [(OctProblem(4, 5, hill_amp=0.8, hill_lat=0.3), 8),
+                                  (OctProblem(16, 8, hill_amp=0.7), 12), (OctProblem(16, 8, hill_amp=0.7), 16)],
+                         ids=["O4x5k8", "O16x8k12", "O16x8k16"])
+def test_gmres_matches_oracle(ft, oracle_mod, case):
+    _say("octahedral gmres", case[0].N, case[1])
+    _gm_parity(ft, oracle_mod, *case)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_gmres_fault_decisions_match_oracle(ft, oracle_mod, case):
+    """An overflowing flip of v_j (caught at its step), a flip of x (caught
+    at the cycle's end), and several events in one run, on O16 x 8."""
+    pb = OctProblem(16, 8, hill_amp=0.7)
+    plans = [
+        [FaultEvent(7, "r", 62, idx=np.array([100, 2000, 3000]))],
+        [FaultEvent(6, "x", 62, idx=np.array([1234]))],
+        [FaultEvent(3, "ap", 62, idx=np.array([5])), FaultEvent(20, "e", 40, start=0, count=pb.n // 10)],
+    ]
+    _say("octahedral gmres faults", case)
+    st = _gm_parity(ft, oracle_mod, pb, 16, plan=plans[case])
+    if case == 0:
+        assert st["detections"] >= 1
