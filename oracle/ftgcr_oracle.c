@@ -1188,14 +1188,32 @@ int orc_oct_mesh(const orc_oct_problem* pb, double* lon, double* lat, double* ar
     return 0;
 }
 
+/* e = r on the O_N mesh: no preconditioner */
+static void oct_identity(const void* cx, const double* r, double* e)
+{
+    const oct_ctx* q = (const oct_ctx*)cx;
+    copy_vec(q->m.ncell * q->m.pb->nz, r, e);
+}
+
 int orc_oct_solve(const orc_oct_problem* pb, const double* rhs, double* x, double tol,
                   int32_t k, int64_t max_steps, int32_t ft, int32_t method,
                   const orc_event* events, int32_t n_events, orc_stats* st,
                   orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
 {
+    return orc_oct_solve_pc(pb, 1, method, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap,
+                            hist, hist_cap);
+}
+
+int orc_oct_solve_pc(const orc_oct_problem* pb, int32_t precond, int32_t method, const double* rhs, double* x,
+                     double tol, int32_t k, int64_t max_steps, int32_t ft,
+                     const orc_event* events, int32_t n_events, orc_stats* st,
+                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap)
+{
+    if (precond != 0 && precond != 1) return -1;
     oct_ctx q;
     op_pair op;
     if (oct_open(pb, &q, &op) != 0) return -1;
+    if (precond == 0) op.apply_pinv = oct_identity;
     const int rc = method == 1
         ? gmres_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap)
         : gcr_core(&op, rhs, x, tol, k, max_steps, ft, events, n_events, st, log, log_cap, hist, hist_cap,

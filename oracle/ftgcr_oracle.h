@@ -190,6 +190,11 @@ int orc_oct_solve(const orc_oct_problem* pb, const double* rhs, double* x, doubl
                   int32_t k, int64_t max_steps, int32_t ft, int32_t method,
                   const orc_event* events, int32_t n_events, orc_stats* st,
                   orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
+/* Same with the column preconditioner (precond 1) or none (precond 0: P = I). */
+int orc_oct_solve_pc(const orc_oct_problem* pb, int32_t precond, int32_t method, const double* rhs, double* x,
+                     double tol, int32_t k, int64_t max_steps, int32_t ft,
+                     const orc_event* events, int32_t n_events, orc_stats* st,
+                     orc_detect* log, int32_t log_cap, double* hist, int64_t hist_cap);
 
 #ifdef __cplusplus
 }

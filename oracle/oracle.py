@@ -124,6 +124,11 @@ def _load():
                                       ctypes.c_int32, ctypes.POINTER(_Event), ctypes.c_int32, ctypes.POINTER(_Stats),
                                       ctypes.POINTER(_Detect), ctypes.c_int32, dp, ctypes.c_int64]
         lib.orc_oct_solve.restype = ctypes.c_int
+        lib.orc_oct_solve_pc.argtypes = [OP, ctypes.c_int32, ctypes.c_int32, dp, dp, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_Event), ctypes.c_int32,
+                                         ctypes.POINTER(_Stats), ctypes.POINTER(_Detect), ctypes.c_int32, dp,
+                                         ctypes.c_int64]
+        lib.orc_oct_solve_pc.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int32]
         lib.orc_set_threads.restype = ctypes.c_int
         lib.orc_threads.argtypes = []
@@ -258,9 +263,13 @@ class OctOracle:
         return _load().orc_dot(self.n, _ptr(_vec(a, self.n)), _ptr(_vec(b, self.n)))
 
     def solve(self, rhs, x0=None, tol: float = 1e-10, k: int = 3, max_steps: int = 100000, ft: bool = True,
-              plan=None, log_cap: int = 4096, hist_cap: Optional[int] = None, method: str = "gcr"):
-        """FT-GCR(k) or FT-GMRES(k) on the O_N problem; returns (x, stats,
+              plan=None, log_cap: int = 4096, hist_cap: Optional[int] = None, method: str = "gcr",
+              precond: str = "column"):
+        """FT-GCR(k) or FT-GMRES(k) on the O_N problem, with the column
+        preconditioner or none (precond 'none': P = I); returns (x, stats,
         detection log, residual history) as Oracle.solve."""
+        if method not in ("gcr", "gmres") or precond not in ("column", "none"):
+            raise ValueError("method is 'gcr' or 'gmres', precond 'column' or 'none'")
         rhs = _vec(rhs, self.n)
         x = np.zeros(self.n) if x0 is None else _vec(x0, self.n).copy()
         keep = []
@@ -270,9 +279,10 @@ class OctOracle:
         hist = np.zeros(max(1, hist_cap))
         log = (_Detect * max(1, log_cap))()
         st = _Stats()
-        rc = _load().orc_oct_solve(ctypes.byref(self._c), _ptr(rhs), _ptr(x), float(tol), int(k), int(max_steps),
-                                   1 if ft else 0, {"gcr": 0, "gmres": 1}[method], events, nev, ctypes.byref(st),
-                                   log, int(log_cap), _ptr(hist), int(hist_cap))
+        rc = _load().orc_oct_solve_pc(ctypes.byref(self._c), 1 if precond == "column" else 0,
+                                      {"gcr": 0, "gmres": 1}[method], _ptr(rhs), _ptr(x), float(tol), int(k),
+                                      int(max_steps), 1 if ft else 0, events, nev, ctypes.byref(st),
+                                      log, int(log_cap), _ptr(hist), int(hist_cap))
         if rc != 0:
             raise ValueError("oracle rejected the arguments")
         stats = {name: getattr(st, name) for name, _ in _Stats._fields_ if name != "pad_"}

@@ -142,7 +142,10 @@ static void octahedral_cases(void)
         for (int method = 0; method < 2; ++method) {
             memset(x, 0, sizeof(double) * (size_t)n);
             EXPECT(orc_oct_solve(&pb, rhs, x, 1e-8, 3, 500, 1, method, ev, 2, &st, log, 2, hist, 5) == 0);
+            memset(x, 0, sizeof(double) * (size_t)n);
+            EXPECT(orc_oct_solve_pc(&pb, 0, method, rhs, x, 1e-8, 3, 500, 1, ev, 2, &st, log, 2, hist, 5) == 0);
         }
+        EXPECT(orc_oct_solve_pc(&pb, 3, 0, rhs, x, 1e-8, 3, 500, 1, NULL, 0, &st, NULL, 0, NULL, 0) == -1);
         free(mu);
         free(w);
         free(lon);

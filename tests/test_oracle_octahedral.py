@@ -172,6 +172,51 @@ def test_solvers_match_dense_lu(oracle_mod, method):
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 2 * np.linalg.cond(m) * 1e-12
 
 
+@pytest.mark.parametrize("method", ["gcr", "gmres"])
+def test_unpreconditioned_solvers_match_dense_lu(oracle_mod, method):
+    o = oracle_mod.OctOracle(_problem(2, 3, amp=0.6))
+    m = o.dense_matrix()
+    rhs = np.random.default_rng(15).uniform(-1, 1, o.n)
+    ref = np.linalg.solve(m, rhs)
+    x, st, _, _ = o.solve(rhs, tol=1e-12, k=8, method=method, precond="none", max_steps=200000)
+    assert st["status"] == oracle_mod.CONVERGED and st["detections"] == 0
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 2 * np.linalg.cond(m) * 1e-12
+
+
+def test_unpreconditioned_gcr_is_conjugate_residual(oracle_mod):
+    """The O_N operator is symmetric, so with P = I every GCR(k) is the
+    conjugate residual method: histories for k = 1, 2, 5 agree with a
+    textbook conjugate-residual recurrence on the dense matrix while well
+    above rounding."""
+    o = oracle_mod.OctOracle(_problem(2, 3, amp=0.6))
+    m = o.dense_matrix()
+    assert np.allclose(m, m.T, rtol=0, atol=1e-13 * np.abs(m).max())
+    rhs = np.random.default_rng(16).uniform(-1, 1, o.n)
+    steps = 50
+    hs = [o.solve(rhs, tol=1e-30, k=k, max_steps=steps, ft=False, precond="none")[3] for k in (1, 2, 5)]
+    r = rhs.copy()
+    p = r.copy()
+    ar = m @ r
+    ap = ar.copy()
+    ref = []
+    for _ in range(steps):
+        rar = r @ ar
+        alpha = rar / (ap @ ap)
+        r = r - alpha * ap
+        ref.append(r @ r)
+        ar = m @ r
+        beta = (r @ ar) / rar
+        p = r + beta * p
+        ap = ar + beta * ap
+    ref = np.array(ref)
+    keep = ref > 1e-16 * (rhs @ rhs)
+    assert keep.sum() >= 20
+    for h in hs:
+        np.testing.assert_allclose(h[:steps][keep], ref[keep], rtol=1e-7)
+    with pytest.raises(ValueError):
+        o.solve(rhs, tol=1e-8, k=3, precond="diagonal")
+
+
 def test_detected_fault_recovers_fault_free_run(oracle_mod):
     from paper_2103_07210_amd.inputs import FaultEvent
     o = oracle_mod.OctOracle(_problem(8, 6))
