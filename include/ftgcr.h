@@ -226,8 +226,7 @@ void ftgcr_default_options(ftgcr_options* opt);
  * cell and face centres, vertical decay, metric factors; on O_N the mesh's
  * neighbour lists, face weights and control areas) and the device state.
  *  grid, coeffs : host, read during the call.  nz <= 96.
- *  precond      : FTGCR_PRECOND_COLUMN or FTGCR_PRECOND_NONE (P = I; the
- *                 lat-lon mesh only).
+ *  precond      : FTGCR_PRECOND_COLUMN or FTGCR_PRECOND_NONE (P = I).
  *  precision    : FTGCR_FP64, or FTGCR_MIXED (lat-lon mesh only).
  *  kmax         : bounds k in later solves (1 <= kmax <= FTGCR_KMAX).
  *  hip_stream   : a hipStream_t (NULL: the default stream).

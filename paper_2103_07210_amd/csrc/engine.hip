@@ -1448,8 +1448,6 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
         return fail(nullptr, FTGCR_E_INVALID, "octahedral grid needs N = nlat in 1..4000 and nz >= 1");
     if (oct && precision != FTGCR_FP64)
         return fail(nullptr, FTGCR_E_UNSUPPORTED, "the octahedral mesh is built for FP64 handles");
-    if (oct && precond != FTGCR_PRECOND_COLUMN)
-        return fail(nullptr, FTGCR_E_UNSUPPORTED, "the octahedral mesh is built with the column preconditioner");
     if (!(grid->shell_depth > 0)) return fail(nullptr, FTGCR_E_INVALID, "shell_depth must be > 0");
     if (!(coeffs->hill_width > 0) || !(coeffs->decay_z > 0) || !(coeffs->hill_amp >= 0) || !(coeffs->helmholtz > 0))
         return fail(nullptr, FTGCR_E_INVALID, "coefficients need hill_width > 0, decay_z > 0, hill_amp >= 0, helmholtz > 0");
