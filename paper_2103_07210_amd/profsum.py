@@ -109,6 +109,9 @@ def pmc(fetch_dir, write_dir, grid, cmd):
                 "k_dir_update<double"):
         fk, n1 = avg_big(pick(fetch, key))
         wk, n2 = avg_big(pick(write, key))
+        if n1 and not n2:   # a pass that writes only its block partials
+            wv = pick(write, key)
+            wk, n2 = (sum(wv) / len(wv), n1) if wv else (0.0, 0)
         if n1 and n2:
             fb, wb = fk * sf * 1024.0, wk * sw * 1024.0
             print(f"| `{key}` | {min(n1, n2)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} |")
