@@ -270,7 +270,7 @@ def main():
     # mixed precision, same problem, time to the same 1e-8 true residual,
     # against FP64 solves timed the same way (no per-kernel events)
     fp64_runs = []
-    for _ in range(3 if args.mixed_steps > 0 else 0):
+    for _ in range(5 if args.mixed_steps > 0 else 0):
         x.zero_()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -287,7 +287,7 @@ def main():
         x.zero_()
         s_off.solve(rhs, x, tol=TOL, k=K)
         off_runs = []
-        for _ in range(3):
+        for _ in range(5):
             x.zero_()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
