@@ -22,6 +22,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ftgcr_internal.h"
 
 using namespace ftgcr;
@@ -29,6 +31,16 @@ using namespace ftgcr;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+
+// A named range on the ROCm tracer's timeline (rocprofv3 --marker-trace):
+// solves, batches, autotuning and refinement rounds.  The allocation-free
+// solve opens none.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -900,8 +912,10 @@ ftgcr_status solve_impl(ftgcr_handle* h, const double* rhs, double* x, double to
             const long long cap = std::min<long long>(max_steps, hs.s + h->opt.inner_max_steps);
             const long long s0 = hs.s;
             L::set_round(tb, tau * tau, cap, s);
+            if (!run.noalloc) roctxRangePushA("ftgcr refinement round");
             run.start_round();
             rc = run.run_steps(s0, cap, evs);
+            if (!run.noalloc) roctxRangePop();
             if (rc != FTGCR_OK) return rc;
             L::finalize_x(tb, h->nblk_st, h->kc, s);
             refinements += 1;
@@ -1563,8 +1577,15 @@ ftgcr_status ftgcr_solve(ftgcr_handle* h, const double* rhs_dev, double* x_dev, 
     if (!h->ws) return fail(h, FTGCR_E_WORKSPACE, "no workspace set");
     if (h->ws_bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "workspace smaller than required by the current options");
     HIP_TRY(h, hipSetDevice(h->device));
-    if (h->opt.method == FTGCR_METHOD_GMRES) return gm_solve_impl(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
-    if (h->precision == FTGCR_MIXED) return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
+    if (h->opt.method == FTGCR_METHOD_GMRES) {
+        TraceRange tr("ftgcr_solve FT-GMRES");
+        return gm_solve_impl(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
+    }
+    if (h->precision == FTGCR_MIXED) {
+        TraceRange tr("ftgcr_solve FT-GCR mixed");
+        return solve_impl<float>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
+    }
+    TraceRange tr("ftgcr_solve FT-GCR FP64");
     return solve_impl<double>(h, rhs_dev, x_dev, tol, k, plan, stats, h->ws);
 }
 
@@ -1598,6 +1619,7 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
                                const double* tol, int32_t k, const ftgcr_fault_plan* plans, ftgcr_stats* stats)
 {
     if (!hs || n < 1 || !rhs || !x || !tol) return FTGCR_E_INVALID;
+    TraceRange tr("ftgcr_solve_batch");
     for (int m = 0; m < n; ++m) {
         ftgcr_handle* h = hs[m];
         if (!h) return FTGCR_E_INVALID;
@@ -1624,6 +1646,7 @@ ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_sc
                             int32_t steps, int32_t* chosen)
 {
     if (!h) return FTGCR_E_INVALID;
+    TraceRange tr("ftgcr_autotune");
     if (!rhs_dev || !x_scratch_dev) return fail(h, FTGCR_E_INVALID, "rhs or x is NULL");
     if (k < 1 || k > h->kmax || steps < 1) return fail(h, FTGCR_E_INVALID, "bad k or steps");
     if (!h->ws || h->ws_bytes < layout(h).total) return fail(h, FTGCR_E_WORKSPACE, "no workspace set");
@@ -1681,6 +1704,7 @@ ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n, const doub
                                   double* const* x_scratch, int32_t k, int32_t steps, int32_t* chosen)
 {
     if (!hs || n < 1 || !rhs || !x_scratch || steps < 1) return FTGCR_E_INVALID;
+    TraceRange tr("ftgcr_autotune_batch");
     for (int m = 0; m < n; ++m)
         if (!hs[m] || !x_scratch[m]) return FTGCR_E_INVALID;
     HIP_TRY(hs[0], hipSetDevice(hs[0]->device));
