@@ -132,7 +132,26 @@ typedef struct {
                                 (FT-GCR(k), Algorithm 1) or FTGCR_METHOD_GMRES
                                 (the same fault layer on restarted GMRES(k);
                                 FP64 handles, single solves)                    */
+    int32_t order_stencil;   /* block order of the stencil-grid passes (the
+                                dots pass of L(e), the residual and the final
+                                x): FTGCR_ORDER_*; 0 = auto (ftgcr_autotune's
+                                choice, else the mesh's default)              */
+    int32_t order_dir;       /* block order of the direction pass, likewise  */
 } ftgcr_options;
+
+/* options.order_stencil / order_dir: the order in which a pass's blocks (a
+ * column tile times a chunk of levels) are assigned to the launch's
+ * workgroups.  The result does not depend on it beyond the order of the
+ * block partial sums.
+ *   X    the tiles of one level chunk in a row, then the next chunk (the
+ *        lat-lon default);
+ *   Z    a tile's level chunks in a row, so its vertical halo levels and
+ *        per-column tables are re-read while still cached;
+ *   XCD  as Z, with each of the GPU's 8 accelerator dies (XCDs, each with its
+ *        own L2; consecutive workgroups go to consecutive dies) given one
+ *        contiguous range of tiles, so neighbouring tiles share an L2 (the
+ *        octahedral default: its slot tables and neighbour gathers). */
+enum { FTGCR_ORDER_AUTO = 0, FTGCR_ORDER_X = 1, FTGCR_ORDER_Z = 2, FTGCR_ORDER_XCD = 3 };
 
 /* options.method.  FTGCR_METHOD_GMRES: right-preconditioned restarted
  * GMRES(k) with classical Gram-Schmidt and Givens rotations, wrapped in the
@@ -217,7 +236,8 @@ typedef struct ftgcr_handle ftgcr_handle;
 /* Fill *opt with defaults: ft=1 (the fault layer of Algorithm 1 on),
  * method=GCR, poll_steps=16, max_steps=100000, inner_tol=3e-5,
  * max_refinements=20, inner_max_steps=5000, hist_cap=65536, use_graphs=1,
- * levels_per_block=0.  opt must not be NULL. */
+ * levels_per_block=0, order_stencil=order_dir=0 (auto).  opt must not be
+ * NULL. */
 void ftgcr_default_options(ftgcr_options* opt);
 
 /* Create a solver for one grid and coefficient set on the current HIP device
@@ -322,15 +342,26 @@ ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n,
                                   const double* const* rhs, double* const* x_scratch,
                                   int32_t k, int32_t steps, int32_t* chosen);
 
-/* Autotuner of the stencil tiling (levels of a column per block) of the
- * operator application L(p) of Algorithm 1 (the results do not depend on
- * the choice beyond the order of the block partial sums): times
- * `steps` steps of this problem for each candidate and keeps the fastest for
- * this handle (options.levels_per_block = 0) and for every later handle with
- * the same grid and precision in this process.  x_scratch_dev: FP64 device
- * buffer of N entries, overwritten.  *chosen (optional) gets the choice. */
+/* Autotuner of the stencil tiling of the operator application L(p) of
+ * Algorithm 1 (the results do not depend on the choice beyond the order of
+ * the block partial sums): times `steps` steps of this problem for each
+ * candidate number of levels of a column per block, then, at the fastest,
+ * each pair of block orders (FTGCR_ORDER_X, _Z, _XCD) of the dots pass and
+ * the direction pass by those kernels' own times, and keeps the fastest for
+ * this handle (options.levels_per_block = 0, order_stencil = order_dir = 0)
+ * and for every later handle with the same mesh, grid and precision in this
+ * process.  x_scratch_dev: FP64 device buffer of N entries, overwritten.
+ * *chosen (optional) gets the levels per block. */
 ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_scratch_dev, int32_t k,
                             int32_t steps, int32_t* chosen);
+
+/* The stencil tiling in effect for this handle's next single solve (from
+ * its options, else ftgcr_autotune's choice, else the defaults): levels of
+ * a column per block of the dots pass and of the direction pass, and the
+ * two passes' block orders (FTGCR_ORDER_X, _Z or _XCD, never AUTO).  Any
+ * output pointer may be NULL. */
+ftgcr_status ftgcr_get_tiling(const ftgcr_handle* h, int32_t* levels_per_block, int32_t* levels_per_block_dir,
+                              int32_t* order_stencil, int32_t* order_dir);
 
 /* Per-kernel device time (measurement of the step of Algorithm 1)
  * accumulated while options.profile_kernels != 0:

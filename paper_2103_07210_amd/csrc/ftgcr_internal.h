@@ -43,6 +43,13 @@ constexpr int RED_THREADS = 1024;
 // is at most 6); a block of the stencil kernels covers ST_THREADS
 // consecutive points.
 constexpr int NB_OCT = 6;
+// Block orders of the stencil-grid launches (a block is a column tile times
+// a chunk of levels; FTGCR_ORDER_* minus 1): tiles of a level chunk in a row
+// (X); a tile's level chunks in a row (Z); as Z, with each accelerator die
+// given one contiguous range of blocks (XCD).  Consecutive workgroups are
+// placed on the XCDS dies round robin, each die with its own L2.
+enum { ORD_X = 0, ORD_Z = 1, ORD_XCD = 2 };
+constexpr int XCDS = 8;
 
 struct DetectRec {
     long long step;
@@ -151,6 +158,8 @@ struct Inst {
     // the direction pass (the most registers per level) has its own level
     // tiling over the same columns
     int nblk_dir, kc_dir, tz_dir;
+    // block orders (ORD_*) of the stencil grid and of the direction grid
+    int ord_st, ord_dir;
 };
 
 // FT-GMRES(k) control state of one solve (device memory; written by single
@@ -194,6 +203,7 @@ struct GmInst {
     double* hist;
     long long hist_cap;
     int nblk_st, kc, tx, ty, tz;
+    int ord;                 // block order (ORD_*) of the stencil kernels
 };
 
 // Launch table for combined (batched) launches: block b of a launch belongs

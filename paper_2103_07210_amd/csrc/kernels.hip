@@ -512,14 +512,37 @@ struct StPos {
     bool col_ok;
 };
 
+// Block lb of a stencil-grid launch of nct column tiles times tz level
+// chunks -> its column tile ct and level chunk bz, in block order `ord`
+// (ORD_X: ct fastest; ORD_Z: bz fastest; ORD_XCD: bz fastest after
+// renumbering, so that the blocks the hardware places on one die (those
+// congruent modulo XCDS) take one contiguous range of the order).  A
+// bijection on [0, nct * tz) for every order.
+__device__ __forceinline__ void block_tile(int lb, int nct, int tz, int ord, int& ct, int& bz)
+{
+    if (ord == ORD_X) {
+        ct = lb % nct;
+        bz = lb / nct;
+        return;
+    }
+    if (ord == ORD_XCD) {
+        const int n = nct * tz;
+        const int q = n / XCDS, r = n % XCDS, d = lb % XCDS;
+        lb = d * q + (d < r ? d : r) + lb / XCDS;
+    }
+    bz = lb % tz;
+    ct = lb / tz;
+}
+
+// Lat-lon: a block is a 64 x 4 tile of columns times kc levels.
 template <typename T>
-__device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb, int kc)
+__device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb, int kc, int ord)
 {
     StPos p;
-    const int bx = lb % in.tx;
-    const int t = lb / in.tx;
-    const int by = t % in.ty;
-    const int bz = t / in.ty;
+    int ct, bz;
+    block_tile(lb, in.tx * in.ty, (in.g.nz + kc - 1) / kc, ord, ct, bz);
+    const int bx = ct % in.tx;
+    const int by = ct / in.tx;
     const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
     const int j = by * ST_TY + (threadIdx.x / ST_TX);
     p.col_ok = i < in.g.nx && j < in.g.ny;
@@ -529,21 +552,15 @@ __device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb, int kc)
     return p;
 }
 
-template <typename T>
-__device__ __forceinline__ StPos st_pos(const Inst<T>& in, int lb)
-{
-    return st_pos(in, lb, in.kc);
-}
-
 // Position on either mesh: lat-lon as above; octahedral (nx = points per
 // level, ny = 1): ST_THREADS consecutive points per block, i = the point.
 template <int MESH, typename T>
-__device__ __forceinline__ StPos st_pos_m(const Inst<T>& in, int lb, int kc)
+__device__ __forceinline__ StPos st_pos_m(const Inst<T>& in, int lb, int kc, int ord)
 {
     if constexpr (MESH == FTGCR_MESH_OCTAHEDRAL) {
         StPos p;
-        const int bx = lb % in.tx;
-        const int bz = lb / in.tx;
+        int bx, bz;
+        block_tile(lb, in.tx, (in.g.nz + kc - 1) / kc, ord, bx, bz);
         const int i = bx * ST_THREADS + threadIdx.x;
         p.col_ok = i < in.g.nx;
         p.i = p.col_ok ? i : in.g.nx - 1;
@@ -551,7 +568,7 @@ __device__ __forceinline__ StPos st_pos_m(const Inst<T>& in, int lb, int kc)
         p.k0 = bz * kc;
         return p;
     } else {
-        return st_pos(in, lb, kc);
+        return st_pos(in, lb, kc, ord);
     }
 }
 
@@ -731,7 +748,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_residual(Table<T> tb, int store)
     const int m = find_inst(tb.blk0_st, tb.n, blockIdx.x);
     const Inst<T>& in = tb.inst[m];
     const int lb = blockIdx.x - tb.blk0_st[m];
-    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc, in.ord_st);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     T* rout = in.R[in.st->r_dst];
@@ -1495,7 +1512,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb, int sp
     const int nu = st->nu;
     if ((int)threadIdx.x <= nu) s_ap[threadIdx.x] = in.AP[st->slot[threadIdx.x]];
     __syncthreads();
-    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc, in.ord_st);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
@@ -1645,7 +1662,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
         s_be[threadIdx.x] = (xupd && (int)threadIdx.x >= xlo) ? st->beta[threadIdx.x] : 0.0;
     }
     __syncthreads();
-    const StPos ps = st_pos_m<MESH>(in, lb, in.kc_dir);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc_dir, in.ord_dir);
     const int nz = in.g.nz;
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
@@ -1767,7 +1784,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_finalize_x(Table<T> tb)
     const SolveState* st = in.st;
     const int lo = st->x_base_nu, hi = st->x_final_hi;
     if (st->x_base == 0 && hi < lo) return;
-    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc, in.ord_st);
     if (!ps.col_ok) return;
     const double* xb = in.X[st->x_base];
     double* xo = in.X[0];
@@ -1895,7 +1912,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_beta_dots(Table<T> tb)
     SolveState* st = in.st;
     if (!st->ev_ok) return;
     const int lb = blockIdx.x;
-    const StPos ps = st_pos_m<MESH>(in, lb, in.kc);
+    const StPos ps = st_pos_m<MESH>(in, lb, in.kc, in.ord_st);
     double an = 0.0, ad = 0.0;
     if (ps.col_ok) {
         const T* r = in.R[st->r_cur];
@@ -1941,7 +1958,7 @@ template <int KC, int MESH>
 __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, const double* x, double* y)
 {
     const Inst<double>& in = tb.inst[0];
-    const StPos ps = st_pos_m<MESH>(in, blockIdx.x, in.kc);
+    const StPos ps = st_pos_m<MESH>(in, blockIdx.x, in.kc, in.ord_st);
     double ax[KC];
     stencil_m<double, KC, MESH>(in.g, x, ps, ax);
 #pragma unroll
@@ -2244,19 +2261,18 @@ template struct Launch<float>;
 __device__ __forceinline__ StPos gm_pos(const GmInst& in, int lb)
 {
     StPos p;
+    int ct, bz;
+    block_tile(lb, in.tx * in.ty, in.tz, in.ord, ct, bz);
     if (in.g.mesh == FTGCR_MESH_OCTAHEDRAL) {   // ST_THREADS consecutive points per block
-        const int bxo = lb % in.tx;
-        const int i = bxo * ST_THREADS + threadIdx.x;
+        const int i = ct * ST_THREADS + threadIdx.x;
         p.col_ok = i < in.g.nx;
         p.i = p.col_ok ? i : in.g.nx - 1;
         p.j = 0;
-        p.k0 = (lb / in.tx) * in.kc;
+        p.k0 = bz * in.kc;
         return p;
     }
-    const int bx = lb % in.tx;
-    const int t = lb / in.tx;
-    const int by = t % in.ty;
-    const int bz = t / in.ty;
+    const int bx = ct % in.tx;
+    const int by = ct / in.tx;
     const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
     const int j = by * ST_TY + (threadIdx.x / ST_TX);
     p.col_ok = i < in.g.nx && j < in.g.ny;

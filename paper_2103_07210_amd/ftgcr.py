@@ -23,6 +23,7 @@ PRECOND_NONE, PRECOND_COLUMN = 0, 1
 CONVERGED, MAX_STEPS, STAGNATED, BREAKDOWN = 0, 1, 2, 3
 METHOD_GCR, METHOD_GMRES = 0, 1
 MESH_LATLON, MESH_OCTAHEDRAL = 0, 1
+ORDER_AUTO, ORDER_X, ORDER_Z, ORDER_XCD = 0, 1, 2, 3
 KMAX = 16
 LOG_CAP = 256
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -31,7 +32,7 @@ EXPORTED = ["ftgcr_default_options", "ftgcr_create", "ftgcr_set_options", "ftgcr
             "ftgcr_set_stream", "ftgcr_workspace_bytes", "ftgcr_set_workspace", "ftgcr_solve",
             "ftgcr_solve_batch", "ftgcr_destroy", "ftgcr_last_error", "ftgcr_debug_apply_A",
             "ftgcr_debug_apply_Pinv", "ftgcr_kernel_times", "ftgcr_reset_kernel_times", "ftgcr_autotune",
-            "ftgcr_autotune_batch", "ftgcr_bw_probe", "ftgcr_solve_noalloc"]
+            "ftgcr_autotune_batch", "ftgcr_bw_probe", "ftgcr_solve_noalloc", "ftgcr_get_tiling"]
 
 
 class FtgcrError(RuntimeError):
@@ -57,7 +58,8 @@ class Options(ctypes.Structure):
                 ("max_refinements", ctypes.c_int32), ("inner_max_steps", ctypes.c_int32),
                 ("hist_cap", ctypes.c_int64), ("use_graphs", ctypes.c_int32),
                 ("levels_per_block", ctypes.c_int32), ("profile_kernels", ctypes.c_int32),
-                ("batch_levels_per_block", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("batch_levels_per_block", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("order_stencil", ctypes.c_int32), ("order_dir", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -143,6 +145,9 @@ def load():
     lib.ftgcr_reset_kernel_times.restype = ctypes.c_int
     lib.ftgcr_autotune.argtypes = [H, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.ftgcr_autotune.restype = ctypes.c_int
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.ftgcr_get_tiling.argtypes = [H, i32p, i32p, i32p, i32p]
+    lib.ftgcr_get_tiling.restype = ctypes.c_int
     lib.ftgcr_autotune_batch.argtypes = [ctypes.POINTER(H), ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.ftgcr_autotune_batch.restype = ctypes.c_int
@@ -332,6 +337,14 @@ class Solver:
                                      ctypes.byref(chosen)), self._h)
         torch.cuda.synchronize()
         return chosen.value
+
+    def tiling(self) -> dict:
+        """The stencil tiling of the next solve: levels per block of the dots
+        and direction passes and their block orders (ORDER_X, _Z, _XCD)."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(load().ftgcr_get_tiling(self._h, *[ctypes.byref(a) for a in v]), self._h)
+        return {"levels_per_block": v[0].value, "levels_per_block_dir": v[1].value,
+                "order_stencil": v[2].value, "order_dir": v[3].value}
 
     def kernel_times(self) -> dict:
         """{kernel name: (launches, total ms)} accumulated while profile_kernels is on."""

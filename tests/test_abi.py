@@ -47,10 +47,13 @@ def test_default_options_and_create_errors_without_gpu(lib):
     assert o.ft == 1 and o.poll_steps == 16 and o.max_steps == 100000
     assert o.inner_tol == 3e-5 and o.hist_cap == 65536
     assert o.batch_levels_per_block == 0 and o.levels_per_block == 0
+    assert o.order_stencil == ftgcr.ORDER_AUTO and o.order_dir == ftgcr.ORDER_AUTO
     # the batch autotuner validates before any device call
     lib.ftgcr_autotune_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
     assert lib.ftgcr_autotune_batch(None, 0, None, None, 3, 8, None) == ftgcr.E_INVALID
+    lib.ftgcr_get_tiling.argtypes = [ctypes.c_void_p] * 5
+    assert lib.ftgcr_get_tiling(None, None, None, None, None) == ftgcr.E_INVALID
     # argument validation happens before any device call
     lib.ftgcr_create.argtypes = [ctypes.POINTER(ftgcr.Grid), ctypes.POINTER(ftgcr.Coeffs), ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
