@@ -204,7 +204,8 @@ def main():
 
     s64 = ftgcr.Solver(pb, "fp64", kmax=K, poll_steps=32)
     kc64 = s64.autotune(rhs, k=K, steps=24) if not args.profile_run else s64.options()["levels_per_block"]
-    print(f"[bench] fp64 stencil tiling: {kc64 or 'automatic'} levels per block", flush=True)
+    til64 = s64.tiling()
+    print(f"[bench] fp64 stencil tiling: {til64}", flush=True)
     for _ in range(args.warmup):
         x.zero_()
         s64.solve(rhs, x, tol=TOL, k=K)
@@ -323,7 +324,8 @@ def main():
         mixed = {"fp64": fp64_ms, "mixed": mixed_med, "speedup": fp64_ms / mixed_med,
                  "fp64_true_residual": stats["rel_res_true"], "mixed_true_residual": mstats["rel_res_true"],
                  "mixed_inner_steps": mstats["steps_executed"], "mixed_refinements": mstats["refinements"],
-                 "mixed_vs_fp64_solution_rel_diff": mixed_err, "mixed_levels_per_block": kcm}
+                 "mixed_vs_fp64_solution_rel_diff": mixed_err, "mixed_levels_per_block": kcm,
+                 "mixed_tiling": sm.tiling()}
         fracs["512x256x64_mixed"] = step_frac(mstats["steps_executed"], K, n, 4, mixed_med,
                                               rounds=mstats["refinements"],
                                               residual_passes=mstats["refinements"] + 1)
@@ -437,10 +439,11 @@ def main():
         _, sfo = so.solve(rhs_o, x_o, tol=TOL, k=5, plan=plan_o)
         torch.cuda.synchronize()
         ms_fo = (time.perf_counter() - t1) * 1e3
+        til_o = so.tiling()
         so.close()
         fr = step_frac(sto["steps_executed"], 5, po.n, 8, ms_o)
         extra["octahedral_O160x51"] = {
-            "points": po.n, "k": 5, "tol": TOL, "levels_per_block": kco, "ms": ms_o,
+            "points": po.n, "k": 5, "tol": TOL, "levels_per_block": kco, "tiling": til_o, "ms": ms_o,
             "steps": sto["steps_executed"], "us_per_step": ms_o * 1e3 / sto["steps_executed"],
             "rel_res_true": sto["rel_res_true"], "alg_gbs": fr["alg_gbs"], "frac": fr["frac"],
             "kernels_us": {q: v[1] / v[0] * 1e3 for q, v in kto.items() if v[0]},
@@ -487,7 +490,7 @@ def main():
             kcl = sl.autotune(rhs_l, k=K, steps=12)
             x_l.zero_()
             sl.solve(rhs_l, x_l, tol=TOL, k=K)
-            rec = {"levels_per_block": kcl}
+            rec = {"levels_per_block": kcl, "tiling": sl.tiling()}
             for name, pln, reps in (("clean", [], 3), ("fault", plan, 1)):
                 runs = []
                 for _ in range(reps):
@@ -532,7 +535,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "FT-GCR(4) FP64 solve to 1e-8, 512x256x64 hill-on-sphere, RHS U[-1,1] seed 3",
                    "grid": list(GRID), "k": K, "tol": TOL, "steps_per_solve": steps_per_solve,
-                   "levels_per_block": kc64},
+                   "levels_per_block": kc64, "tiling": til64},
         "hbm_gbs_algorithmic": whole_gbs,
         "step_frac": fracs,
         "time_to_1e-8_ms": mixed,

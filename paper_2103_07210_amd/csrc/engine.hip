@@ -1007,7 +1007,11 @@ GmInst make_gm_inst(const ftgcr_handle* h, const double* rhs, double* x, void* w
     gi.tx = h->tx;
     gi.ty = h->ty;
     gi.tz = h->tz;
-    gi.ord = h->ord_st;
+    // the option, else the mesh's default (the autotuner's choice is made
+    // for the FT-GCR passes)
+    const int os = h->opt.order_stencil;
+    gi.ord = (os >= FTGCR_ORDER_X && os <= FTGCR_ORDER_XCD) ? os - 1
+                                                           : (h->geo.mesh == FTGCR_MESH_OCTAHEDRAL ? ORD_XCD : ORD_X);
     return gi;
 }
 

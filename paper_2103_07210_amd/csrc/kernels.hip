@@ -1089,7 +1089,7 @@ __device__ __forceinline__ void update_thomas_body(Table<T> tb, const T* dbg_in,
     // exceed 256 and the kernel drops to one wave per SIMD.  binary32 values
     // are half the bytes per load, so it streams 16 levels ahead where the
     // half column allows (more bytes in flight per wave)
-    constexpr int CHW = sizeof(T) == 8 ? 4 : (H % 16 == 0 ? 16 : 8);
+    constexpr int CHW = sizeof(T) == 8 ? 4 : (H % 16 == 0 ? 16 : (H % 8 == 0 ? 8 : 4));
     constexpr int CH = H < CHW ? H : CHW;
     constexpr int NCH = H / CH;
     static_assert(H % CH == 0, "chunks must tile the half column");
@@ -1996,14 +1996,19 @@ __global__ __launch_bounds__(ST_THREADS) void k_debug_apply_A(Table<double> tb, 
     case 8: { constexpr int HV = 8; CALL; } break;        \
     case 16: { constexpr int HV = 16; CALL; } break;      \
     case 24: { constexpr int HV = 24; CALL; } break;      \
+    case 28: { constexpr int HV = 28; CALL; } break;      \
     case 32: { constexpr int HV = 32; CALL; } break;      \
     default: { constexpr int HV = 48; CALL; } break;      \
     }
 
+// Half-column depth of the column pass: the smallest template depth that
+// holds (nz + 1) / 2 levels (28 serves the paper's 51-level O_N columns,
+// half columns of 26, with 8 phantom rows instead of 12 at 32: 44.5 ->
+// 41.4 us per launch on O160 x 51).
 int thomas_depth(int nz)
 {
     const int h = (nz + 1) / 2;
-    const int depths[] = {4, 8, 16, 24, 32, 48};
+    const int depths[] = {4, 8, 16, 24, 28, 32, 48};
     for (int d : depths)
         if (h <= d) return d;
     return -1;

@@ -61,7 +61,8 @@ def _decisions(log):
     return [(d["step"], d["nu"], d["action"]) for d in log]
 
 
-SHAPES = [(64, 32, 8), (100, 7, 5), (3, 1, 1), (70, 9, 33), (128, 64, 16), (64, 8, 96), (200, 30, 2)]
+SHAPES = [(64, 32, 8), (100, 7, 5), (3, 1, 1), (70, 9, 33), (128, 64, 16), (64, 8, 96), (200, 30, 2),
+          (66, 6, 55), (64, 8, 56)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -498,10 +499,11 @@ def test_autotune_keeps_results(ft, oracle_mod):
 
 
 @pytest.mark.parametrize("shape,kc", [((70, 9, 33), 1), ((70, 9, 33), 16), ((64, 8, 96), 2), ((64, 8, 96), 8),
-                                      ((130, 5, 7), 4)])
+                                      ((130, 5, 7), 4), ((66, 6, 55), 8), ((64, 8, 56), 4)])
 def test_solve_parity_across_tilings(ft, oracle_mod, shape, kc):
-    """Odd and maximal column heights (nz 33 and 96: half columns of 17 and
-    48 levels), ragged tiles in x and y, and every level tiling (the dots
+    """Odd and maximal column heights (nz 33, 55 and 96: half columns of 17,
+    28 and 48 levels; nz 56 fills 28-level halves exactly, on whole
+    128-column blocks), ragged tiles in x and y, and every level tiling (the dots
     pass at kc levels per block, the direction pass at min(kc, 4)), with a
     fault in the run: the same decisions, x within 1e-10 at equal steps."""
     _say("tiling", shape, kc)
@@ -520,7 +522,7 @@ def test_solve_parity_across_tilings(ft, oracle_mod, shape, kc):
     assert _rel(x.cpu().numpy(), xe) <= 1e-10
 
 
-@pytest.mark.parametrize("shape,kc", [((70, 9, 33), 16), ((64, 8, 96), 4)])
+@pytest.mark.parametrize("shape,kc", [((70, 9, 33), 16), ((64, 8, 96), 4), ((64, 8, 56), 8)])
 def test_mixed_across_tilings(ft, oracle_mod, shape, kc):
     """The mixed form on odd and maximal column heights (binary32 column
     solve with 17- and 48-level half columns) and other tilings: the FP64
