@@ -2441,6 +2441,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_gm_restart(const GmInst* gi)
 }
 
 // The partials of <w, v_i>, i <= j, of a block's cells (rows DOT_ROW0 + i).
+// The loop over i is unrolled to KMAX with a uniform guard, and the loads of
+// v_{i+1} are issued before v_i's values are used (two buffers alternating
+// with the parity of i), so the terms cost one memory round trip together
+// rather than one each.
 template <int KC>
 __device__ __forceinline__ void gm_dots(const GmInst& in, const StPos& ps, const double (&w)[KC], int j)
 {
@@ -2449,18 +2453,32 @@ __device__ __forceinline__ void gm_dots(const GmInst& in, const StPos& ps, const
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = 0; i <= j; ++i) {
-        const double* vi = in.U[i];
-        double acc = 0.0;
+    double buf[2][KC];
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const bool ok = ps.col_ok && ps.k0 + kk < nz;
-            const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-            const double vv = vi[c0 + plane * kq];
-            acc = fma(w[kk], ok ? vv : 0.0, acc);
+    for (int kk = 0; kk < KC; ++kk) {
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        buf[0][kk] = in.U[0][c0 + plane * kq];
+    }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        if (i <= j) {
+            if (i + 1 < KMAX && i + 1 <= j) {
+                const double* vn = in.U[i + 1];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                    buf[(i + 1) & 1][kk] = vn[c0 + plane * kq];
+                }
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const bool ok = ps.col_ok && ps.k0 + kk < nz;
+                acc = fma(w[kk], ok ? buf[i & 1][kk] : 0.0, acc);
+            }
+            const double t = wave_sum(acc);
+            if (lane == 0) sh[i][wv] = t;
         }
-        const double t = wave_sum(acc);
-        if (lane == 0) sh[i][wv] = t;
     }
     __syncthreads();
     if ((int)threadIdx.x <= j) {
@@ -2525,6 +2543,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_gm_finish_h(const GmInst* gi)
 }
 
 // U[j+1] = w - sum_i h_ij v_i (ascending i); partials of its squared norm.
+// Each cell takes the same operations in the same order as a loop over i
+// per cell; the loop over i runs outside (unrolled to KMAX, uniform guard)
+// with v_{i+1}'s loads issued before v_i is used.
 template <int KC>
 __global__ __launch_bounds__(ST_THREADS) void k_gm_orth(const GmInst* gi)
 {
@@ -2541,16 +2562,36 @@ __global__ __launch_bounds__(ST_THREADS) void k_gm_orth(const GmInst* gi)
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double* un = in.U[j + 1];
+    double w[KC], buf[2][KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        const long long c = c0 + plane * kq;
+        w[kk] = in.W[c];
+        buf[0][kk] = in.U[0][c];
+    }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        if (i <= j) {
+            if (i + 1 < KMAX && i + 1 <= j) {
+                const double* vn = in.U[i + 1];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                    buf[(i + 1) & 1][kk] = vn[c0 + plane * kq];
+                }
+            }
+            const double h = s_h[i];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) w[kk] = w[kk] - h * buf[i & 1][kk];
+        }
+    }
     double acc = 0.0;
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const bool ok = ps.col_ok && ps.k0 + kk < nz;
-        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
-        const long long c = c0 + plane * kq;
-        double w = in.W[c];
-        for (int i = 0; i <= j; ++i) w = w - s_h[i] * in.U[i][c];
-        if (ok) un[c] = w;
-        const double wd = ok ? w : 0.0;
+        if (ok) un[c0 + plane * (ps.k0 + kk)] = w[kk];
+        const double wd = ok ? w[kk] : 0.0;
         acc = fma(wd, wd, acc);
     }
     const double sw = block_sum(acc, sh);
@@ -2660,13 +2701,36 @@ __global__ __launch_bounds__(ST_THREADS) void k_gm_xupd(const GmInst* gi)
     const int xd = (st->x_cur == st->x_bak) ? 1 - st->x_cur : st->x_cur;
     const double* xsrc = in.X[xs];
     double* xdst = in.X[xd];
+    // per cell x + y_0 z_0 + y_1 z_1 + ... in ascending i, the loop over i
+    // outside (unrolled to KMAX, uniform guard) with z_{i+1}'s loads issued
+    // before z_i is used
+    double xv[KC], buf[2][KC];
+#pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-        if (ps.k0 + kk >= nz) break;
-        const long long c = c0 + plane * (ps.k0 + kk);
-        double xv = xsrc[c];
-        for (int i = 0; i < jd; ++i) xv = xv + y[i] * in.Z[i][c];
-        xdst[c] = xv;
+        const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+        const long long c = c0 + plane * kq;
+        xv[kk] = xsrc[c];
+        buf[0][kk] = jd > 0 ? in.Z[0][c] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        if (i < jd) {
+            if (i + 1 < KMAX && i + 1 < jd) {
+                const double* zn = in.Z[i + 1];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                    buf[(i + 1) & 1][kk] = zn[c0 + plane * kq];
+                }
+            }
+            const double yi = y[i];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) xv[kk] = xv[kk] + yi * buf[i & 1][kk];
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+        if (ps.k0 + kk < nz) xdst[c0 + plane * (ps.k0 + kk)] = xv[kk];
 }
 
 __global__ void k_gm_finish_x(const GmInst* gi)
