@@ -85,8 +85,9 @@ enum { FTGCR_CONVERGED = 0, FTGCR_MAX_STEPS = 1, FTGCR_STAGNATED = 2, FTGCR_BREA
  *   the polar caps stay open: no flux through the poles): the control area
  *   of a point is its circumcentric region of the inscribed polyhedron, the
  *   horizontal face weight of an edge is c dz (cot a + cot b) / 2 (the angles
- *   opposite it), the vertical ones c area / dz, c at the face centre.  FP64
- *   handles, FT-GCR, single solves. */
+ *   opposite it), the vertical ones c area / dz, c at the face centre.
+ *   Single solves: FT-GCR in FP64 or MIXED (binary32 copies of the tables),
+ *   FT-GMRES in FP64. */
 enum { FTGCR_MESH_LATLON = 0, FTGCR_MESH_OCTAHEDRAL = 1 };
 
 typedef struct {
@@ -244,10 +245,11 @@ void ftgcr_default_options(ftgcr_options* opt);
  * (the operator L of Eq. (1) discretised as described at the top; the
  * preconditioner of Section 2).  Builds the FP64 coefficient tables (hill at
  * cell and face centres, vertical decay, metric factors; on O_N the mesh's
- * neighbour lists, face weights and control areas) and the device state.
+ * neighbour lists, face weights and control areas), binary32 copies of the
+ * per-column and per-point ones, and the device state.
  *  grid, coeffs : host, read during the call.  nz <= 96.
  *  precond      : FTGCR_PRECOND_COLUMN or FTGCR_PRECOND_NONE (P = I).
- *  precision    : FTGCR_FP64, or FTGCR_MIXED (lat-lon mesh only).
+ *  precision    : FTGCR_FP64 or FTGCR_MIXED (either mesh).
  *  kmax         : bounds k in later solves (1 <= kmax <= FTGCR_KMAX).
  *  hip_stream   : a hipStream_t (NULL: the default stream).
  *  out          : receives the handle (NULL on failure); free with
@@ -347,7 +349,8 @@ ftgcr_status ftgcr_autotune_batch(ftgcr_handle* const* hs, int32_t n,
  * the block partial sums): times `steps` steps of this problem for each
  * candidate number of levels of a column per block, then, at the fastest,
  * each pair of block orders (FTGCR_ORDER_X, _Z, _XCD) of the dots pass and
- * the direction pass by those kernels' own times, and keeps the fastest for
+ * the direction pass by those kernels' own times (the mesh's default pair
+ * unless another is at least 1% faster), and keeps the fastest for
  * this handle (options.levels_per_block = 0, order_stencil = order_dir = 0)
  * and for every later handle with the same mesh, grid and precision in this
  * process.  x_scratch_dev: FP64 device buffer of N entries, overwritten.

@@ -495,9 +495,11 @@ ftgcr_status upload_tables_oct(ftgcr_handle* h)
     std::vector<double> gc(nz), gf(nz + 1);
     for (int k = 0; k < nz; ++k) gc[k] = std::exp(-((k + 0.5) / nz) / co.decay_z);
     for (int k = 0; k <= nz; ++k) gf[k] = std::exp(-((double)k / nz) / co.decay_z);
-    // one device allocation: doubles first, then the slot ids
+    // one device allocation: doubles first, then the slot ids, then binary32
+    // copies of the weight and per-point tables (the mixed form's)
     const size_t nd = 2 * nq + 4 * (size_t)np + nz + (nz + 1);
-    HIP_TRY(h, hipMalloc(&h->tables, nd * sizeof(double) + nq * sizeof(int)));
+    const size_t n32 = 2 * nq + 4 * (size_t)np;
+    HIP_TRY(h, hipMalloc(&h->tables, nd * sizeof(double) + nq * sizeof(int) + n32 * sizeof(float)));
     double* t = h->tables;
     auto put = [&](const double* src, size_t cnt) -> double* {
         double* at = t;
@@ -523,6 +525,18 @@ ftgcr_status upload_tables_oct(ftgcr_handle* h)
     int* ids = reinterpret_cast<int*>(t);
     HIP_TRY(h, hipMemcpy(ids, onb.data(), nq * sizeof(int), hipMemcpyHostToDevice));
     g.onb = ids;
+    std::vector<float> t32;
+    t32.reserve(n32);
+    for (const std::vector<double>* v : {&ogw, &ohw, &oh0, &oh1, &ogz, &ohc})
+        for (double d : *v) t32.push_back((float)d);
+    float* f32 = reinterpret_cast<float*>(ids + nq);
+    HIP_TRY(h, hipMemcpy(f32, t32.data(), n32 * sizeof(float), hipMemcpyHostToDevice));
+    g.ogw32 = f32;
+    g.ohw32 = g.ogw32 + nq;
+    g.oh0_32 = g.ohw32 + nq;
+    g.oh1_32 = g.oh0_32 + np;
+    g.ogz32 = g.oh1_32 + np;
+    g.ohc32 = g.ogz32 + np;
     if (!g.ogw || !g.ohw || !g.oh0 || !g.oh1 || !g.ogz || !g.ohc || !g.gc || !g.gf)
         return fail(h, FTGCR_E_HIP, "octahedral table upload failed");
     return FTGCR_OK;
@@ -1497,8 +1511,6 @@ ftgcr_status ftgcr_create(const ftgcr_grid* grid, const ftgcr_coeffs* coeffs, ft
         return fail(nullptr, FTGCR_E_INVALID, "grid needs nlon >= 3, nlat >= 1, nz >= 1");
     if (oct && (grid->nlat < 1 || grid->nlat > 4000 || grid->nz < 1))
         return fail(nullptr, FTGCR_E_INVALID, "octahedral grid needs N = nlat in 1..4000 and nz >= 1");
-    if (oct && precision != FTGCR_FP64)
-        return fail(nullptr, FTGCR_E_UNSUPPORTED, "the octahedral mesh is built for FP64 handles");
     if (!(grid->shell_depth > 0)) return fail(nullptr, FTGCR_E_INVALID, "shell_depth must be > 0");
     if (!(coeffs->hill_width > 0) || !(coeffs->decay_z > 0) || !(coeffs->hill_amp >= 0) || !(coeffs->helmholtz > 0))
         return fail(nullptr, FTGCR_E_INVALID, "coefficients need hill_width > 0, decay_z > 0, hill_amp >= 0, helmholtz > 0");
@@ -1726,9 +1738,12 @@ ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_sc
     if ((tu.ord_st < 0 || tu.ord_dir < 0) && saved.method == FTGCR_METHOD_GCR) {
         // block orders at that tiling: every pair for the dots pass and the
         // direction pass, by the two kernels' own mean launch times (the
-        // pair, since one pass's order changes what the other finds cached);
-        // the handle's kernel-time totals are kept aside meanwhile
-        double kt_ms[3], best_t = 0.0;
+        // pair, since one pass's order changes what the other finds cached).
+        // The mesh's default pair stays unless another is at least 1%
+        // faster, so that timing noise does not pick between equals.  The
+        // handle's kernel-time totals are kept aside meanwhile.
+        const int def = h->geo.mesh == FTGCR_MESH_OCTAHEDRAL ? ORD_XCD : ORD_X;
+        double kt_ms[3], best_t = 0.0, def_t = 0.0;
         long long kt_n[3];
         std::memcpy(kt_ms, h->kt_ms, sizeof kt_ms);
         std::memcpy(kt_n, h->kt_n, sizeof kt_n);
@@ -1760,7 +1775,12 @@ ftgcr_status ftgcr_autotune(ftgcr_handle* h, const double* rhs_dev, double* x_sc
                     tu.ord_dir = od;
                     best_t = t_min;
                 }
+                if (os == def && od == def) def_t = t_min;
             }
+        }
+        if (rc == FTGCR_OK && !(best_t < 0.99 * def_t)) {
+            tu.ord_st = def;
+            tu.ord_dir = def;
         }
         std::memcpy(h->kt_ms, kt_ms, sizeof kt_ms);
         std::memcpy(h->kt_n, kt_n, sizeof kt_n);

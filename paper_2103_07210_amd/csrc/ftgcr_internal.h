@@ -134,6 +134,14 @@ struct Geo {
     const double* oh1;
     const double* ogz;
     const double* ohc;
+    // binary32 copies of the octahedral tables (rounded to nearest), read by
+    // the binary32 stencil and column solve of the mixed form
+    const float* ogw32;
+    const float* ohw32;
+    const float* oh0_32;
+    const float* oh1_32;
+    const float* ogz32;
+    const float* ohc32;
 };
 
 // Everything one instance's kernels need (device copy per solve).

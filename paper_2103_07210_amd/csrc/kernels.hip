@@ -305,15 +305,20 @@ __device__ __forceinline__ typename RowOf<AT>::type row_consts_for(const Geo& g,
 template <typename AT>
 __device__ __forceinline__ typename RowOf<AT>::type col_consts_for(const Geo& g, int i, int j)
 {
-    if constexpr (sizeof(AT) == 8) {
-        if (g.mesh == FTGCR_MESH_OCTAHEDRAL) {
-            RowC r = {};
+    if (g.mesh == FTGCR_MESH_OCTAHEDRAL) {
+        typename RowOf<AT>::type r = {};
+        if constexpr (sizeof(AT) == 8) {
             r.h0 = g.oh0[i];
             r.h1 = g.oh1[i];
             r.gz = g.ogz[i];
             r.hc = g.ohc[i];
-            return r;
+        } else {
+            r.h0 = g.oh0_32[i];
+            r.h1 = g.oh1_32[i];
+            r.gz = g.ogz32[i];
+            r.hc = g.ohc32[i];
         }
+        return r;
     }
     return row_consts_for<AT>(g, i, j);
 }
@@ -572,19 +577,32 @@ __device__ __forceinline__ StPos st_pos_m(const Inst<T>& in, int lb, int kc, int
     }
 }
 
+// A table entry of the octahedral mesh in the arithmetic type: the FP64
+// table, or its binary32 copy (rounded to nearest) for binary32 arithmetic.
+template <typename AT>
+__device__ __forceinline__ AT oct_tab(const double* d, const float* f, long long q)
+{
+    if constexpr (sizeof(AT) == 8) return d[q];
+    else return f[q];
+}
+
 // (A x) at levels k0 .. k0+KC-1 of point c of the octahedral mesh, in the
 // same operation order as a lat-lon row (off-diagonal sums of metric and
 // metric-times-hill terms, combined with g_k; diagonal h0 + g_k h1 plus the
 // vertical faces, as the column solve forms it), neighbours gathered through
 // the slot tables; an empty slot contributes a selected 0, not a product.
-template <int KC>
-__device__ __forceinline__ void stencil_oct(const Geo& g, const double* __restrict__ x, int c, int k0,
+// The arithmetic runs in the vector type (binary32 vectors: binary32 tables
+// and arithmetic, as on the lat-lon mesh).
+template <typename TI, int KC>
+__device__ __forceinline__ void stencil_oct(const Geo& g, const TI* __restrict__ x, int c, int k0,
                                             double (&out)[KC], double* centre = nullptr)
 {
+    using AT = TI;
     const int nz = g.nz;
     const long long plane = (long long)g.ncols;
-    const double h0 = g.oh0[c], h1 = g.oh1[c], gz = g.ogz[c], hc = g.ohc[c];
-    double xv[KC + 2], t1[KC], t2[KC];
+    const AT h0 = oct_tab<AT>(g.oh0, g.oh0_32, c), h1 = oct_tab<AT>(g.oh1, g.oh1_32, c);
+    const AT gz = oct_tab<AT>(g.ogz, g.ogz32, c), hc = oct_tab<AT>(g.ohc, g.ohc32, c);
+    AT xv[KC + 2], t1[KC], t2[KC];
 #pragma unroll
     for (int t = 0; t < KC + 2; ++t) {
         int k = k0 - 1 + t;
@@ -593,57 +611,56 @@ __device__ __forceinline__ void stencil_oct(const Geo& g, const double* __restri
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-        t1[kk] = 0.0;
-        t2[kk] = 0.0;
+        t1[kk] = AT(0);
+        t2[kk] = AT(0);
     }
 #pragma unroll
     for (int q = 0; q < NB_OCT; ++q) {
         const long long slot = (long long)q * g.ncols + c;
         const int nb = g.onb[slot];
-        const double gw = g.ogw[slot], hw = g.ohw[slot];
+        const AT gw = oct_tab<AT>(g.ogw, g.ogw32, slot), hw = oct_tab<AT>(g.ohw, g.ohw32, slot);
         const long long base = nb >= 0 ? nb : c;
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int k = (k0 + kk > nz - 1) ? nz - 1 : k0 + kk;
-            const double v = x[base + plane * k];
-            const double vs = nb >= 0 ? v : 0.0;
+            const AT v = x[base + plane * k];
+            const AT vs = nb >= 0 ? v : AT(0);
             t1[kk] = fma(gw, vs, t1[kk]);
             t2[kk] = fma(hw, vs, t2[kk]);
         }
     }
-    double wf[KC + 1];
+    AT wf[KC + 1];
 #pragma unroll
     for (int t = 0; t <= KC; ++t) {
         const int f = k0 + t;
         const int fq = f > nz ? nz : f;
-        wf[t] = (f > 0 && f < nz) ? gz * fma(hc, g.gf[fq], 1.0) : 0.0;
+        wf[t] = (f > 0 && f < nz) ? gz * fma(hc, (AT)g.gf[fq], AT(1)) : AT(0);
     }
-    const double opsig = g.opsig;
+    const AT opsig = (AT)g.opsig;
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
         const int kq = (k > nz - 1) ? nz - 1 : k;
-        const double gk = g.gc[kq];
-        const double wb = wf[kk], wa = wf[kk + 1];
-        const double xb = (k > 0) ? xv[kk] : 0.0;
-        const double xa = (k + 1 < nz) ? xv[kk + 2] : 0.0;
-        double off = fma(gk, t2[kk], t1[kk]);
+        const AT gk = (AT)g.gc[kq];
+        const AT wb = wf[kk], wa = wf[kk + 1];
+        const AT xb = (k > 0) ? xv[kk] : AT(0);
+        const AT xa = (k + 1 < nz) ? xv[kk + 2] : AT(0);
+        AT off = fma(gk, t2[kk], t1[kk]);
         off = fma(wb, xb, off);
         off = fma(wa, xa, off);
-        const double diag = opsig * ((fma(gk, h1, h0) + wb) + wa);
-        out[kk] = fma(diag, xv[kk + 1], -off);
-        if (centre) centre[kk] = xv[kk + 1];
+        const AT diag = opsig * ((fma(gk, h1, h0) + wb) + wa);
+        out[kk] = (double)fma(diag, xv[kk + 1], -off);
+        if (centre) centre[kk] = (double)xv[kk + 1];
     }
 }
 
-// The stencil on either mesh (the octahedral one is FP64 only).
+// The stencil on either mesh.
 template <typename TI, int KC, int MESH>
 __device__ __forceinline__ void stencil_m(const Geo& g, const TI* __restrict__ x, const StPos& ps, double (&out)[KC],
                                           double* centre = nullptr)
 {
     if constexpr (MESH == FTGCR_MESH_OCTAHEDRAL) {
-        static_assert(sizeof(TI) == 8, "octahedral mesh: FP64");
-        stencil_oct<KC>(g, x, ps.i, ps.k0, out, centre);
+        stencil_oct<TI, KC>(g, x, ps.i, ps.k0, out, centre);
     } else {
         stencil_chunk<TI, KC>(g, x, ps.i, ps.j, ps.k0, out, centre);
     }
@@ -1308,7 +1325,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_update_thomas1(Table<T> tb)
     const int j = colc / nx;
     const int i = colc - j * nx;
     const long long plane = (long long)ncols;
-    const RowCf rcst = row_consts32(g, i, j);
+    const RowCf rcst = col_consts_for<float>(g, i, j);
     const CT h0 = rcst.h0;
     const CT h1 = rcst.h1;
     const CT gz = rcst.gz, hc = rcst.hc;
@@ -2028,14 +2045,12 @@ void Launch<T>::set_round(const Table<T>& tb, double tol2, long long max_steps, 
     hipLaunchKernelGGL(k_set_round<T>, dim3(tb.n), dim3(64), 0, s, tb, tol2, max_steps);
 }
 
-// A stencil-pass launch on the table's mesh (the octahedral mesh: FP64).
+// A stencil-pass launch on the table's mesh.
 #define FTGCR_MESH_LAUNCH(tb, LAUNCH0, LAUNCH1)                                   \
     do {                                                                          \
         if ((tb).mesh == FTGCR_MESH_OCTAHEDRAL) {                                 \
-            if constexpr (sizeof(T) == 8) {                                       \
-                constexpr int MESHV = FTGCR_MESH_OCTAHEDRAL;                      \
-                LAUNCH1;                                                          \
-            }                                                                     \
+            constexpr int MESHV = FTGCR_MESH_OCTAHEDRAL;                          \
+            LAUNCH1;                                                              \
         } else {                                                                  \
             constexpr int MESHV = FTGCR_MESH_LATLON;                              \
             LAUNCH0;                                                              \
@@ -2196,7 +2211,6 @@ template <>
 void Launch<double>::debug_apply_A(const Table<double>& tb, int total, int kc, const double* in, double* out,
                                    hipStream_t s)
 {
-    using T = double;
     FTGCR_MESH_LAUNCH(tb,
         FTGCR_KC_SWITCH(kc, hipLaunchKernelGGL((k_debug_apply_A<KCV, MESHV>), dim3(total), dim3(ST_THREADS), 0, s, tb,
                                                in, out)),

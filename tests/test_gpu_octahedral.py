@@ -189,3 +189,59 @@ def test_gmres_fault_decisions_match_oracle(ft, oracle_mod, case):
     st = _gm_parity(ft, oracle_mod, pb, 16, plan=plans[case])
     if case == 0:
         assert st["detections"] >= 1
+
+
+@pytest.mark.parametrize("case", [(OctProblem(16, 8, hill_amp=0.7), 4), (I.O40, 5)], ids=["O16x8k4", "O40x51k5"])
+def test_mixed_reaches_true_residual(ft, oracle_mod, case):
+    """The mixed form on O_N (binary32 tables, vectors, stencil and column
+    solve; FP64 inner products, detector and refinement): the FP64 true
+    residual, evaluated with the oracle's operator, meets the tolerance, and
+    x is within kappa * tol (kappa about 2e3) of the FP64 oracle's solution."""
+    pb, k = case
+    _say("octahedral mixed", pb.N, pb.nz, k)
+    rhs = np.random.default_rng(11).uniform(-1.0, 1.0, pb.n)
+    s = ft.Solver(pb, "mixed", kmax=k)
+    x, st = s.solve(rhs, tol=1e-8, k=k)
+    s.close()
+    assert st["status"] == ft.CONVERGED and st["refinements"] >= 1
+    o = oracle_mod.OctOracle(pb)
+    xn = x.cpu().numpy().ravel()
+    true = o.true_residual(xn, rhs)
+    assert true <= 1.001e-8, true
+    xo, so, _, _ = o.solve(rhs, tol=1e-12, k=k)
+    err = float(np.abs(xn - xo).max() / np.abs(xo).max())
+    _say(f"mixed steps {st['steps_executed']} (FP64 oracle to 1e-12: {so['steps_executed']}), "
+         f"true residual {true:.2e}, x error {err:.1e}")
+    assert err <= 2e-5, err
+
+
+def test_mixed_detects_r_fault(ft, oracle_mod):
+    """A binary32 exponent flip (bit 30) of every 7th entry of r at step 5
+    of a mixed O_N solve is caught at that step, and the solve still meets
+    the FP64 true residual."""
+    pb = OctProblem(16, 8, hill_amp=0.7)
+    rhs = np.random.default_rng(12).uniform(-1.0, 1.0, pb.n)
+    plan = [FaultEvent(5, "r", 30, idx=np.arange(0, pb.n, 7))]
+    s = ft.Solver(pb, "mixed", kmax=4)
+    _say("octahedral mixed fault")
+    x, st = s.solve(rhs, tol=1e-8, k=4, plan=plan)
+    s.close()
+    assert st["status"] == ft.CONVERGED and st["events_applied"] == 1
+    assert _decisions(st["log"])[0][0] == 5
+    true = oracle_mod.OctOracle(pb).true_residual(x.cpu().numpy().ravel(), rhs)
+    assert true <= 1.001e-8, true
+
+
+def test_o160_51_levels_mixed(ft, oracle_mod):
+    """The paper's O160 x 51 levels in the mixed form, FT-GCR(5) to 1e-8 on
+    the FP64 true residual (oracle's operator)."""
+    pb = I.O160
+    rhs = np.random.default_rng(160).uniform(-1.0, 1.0, pb.n)
+    s = ft.Solver(pb, "mixed", kmax=5)
+    _say("O160x51 mixed")
+    x, st = s.solve(rhs, tol=1e-8, k=5)
+    s.close()
+    assert st["status"] == ft.CONVERGED
+    true = oracle_mod.OctOracle(pb).true_residual(x.cpu().numpy().ravel(), rhs)
+    _say(f"O160 mixed: {st['steps_executed']} inner steps, {st['refinements']} refinements, true {true:.2e}")
+    assert true <= 1.01e-8, true
