@@ -321,8 +321,9 @@ ftgcr_status ftgcr_solve_noalloc(ftgcr_handle* h, const double* rhs_dev, double*
 
 /* Solve n independent problems at once (an ensemble of the elliptic solves
  * of Eq. (1), each with FT-GCR(k) of Algorithm 1): every handle must be FP64,
- * lat-lon, GCR, with the same preconditioner, have its own workspace and
- * share the first handle's stream; their
+ * GCR, on the first handle's mesh (either mesh), with the same
+ * preconditioner, have its own workspace and share the first handle's
+ * stream; their
  * step kernels run as combined launches over all unfinished members, each
  * member keeping its own convergence and fault state on the device.
  * rhs[m], x[m], tol[m] as in ftgcr_solve; plans may be NULL (no faults) or an

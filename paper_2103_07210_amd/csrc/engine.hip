@@ -1226,7 +1226,7 @@ ftgcr_status upload_batch(ftgcr_handle* h0, const std::vector<Inst<double>>& ins
     sh.cols = pre[na];
     sh.sts = pre[2 * na + 1];
     sh.dirs = pre[3 * na + 2];
-    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na, FTGCR_MESH_LATLON, h0->precond,
+    tb = Table<double>{inst, blk0, blk0 + na + 1, blk0 + 2 * (na + 1), na, h0->geo.mesh, h0->precond,
                        full ? 1 : 0};
     return FTGCR_OK;
 }
@@ -1676,8 +1676,8 @@ ftgcr_status ftgcr_solve_batch(ftgcr_handle* const* hs, int32_t n, const double*
         if (h->precision != FTGCR_FP64) return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are FP64 only");
         if (h->opt.method != FTGCR_METHOD_GCR)
             return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves run FT-GCR (options.method of every member)");
-        if (h->geo.mesh != FTGCR_MESH_LATLON)
-            return fail(hs[0], FTGCR_E_UNSUPPORTED, "batched solves are built for the lat-lon mesh");
+        if (h->geo.mesh != hs[0]->geo.mesh)
+            return fail(hs[0], FTGCR_E_UNSUPPORTED, "batch members on different meshes");
         if (h->precond != hs[0]->precond)
             return fail(hs[0], FTGCR_E_INVALID, "batch members with different preconditioners");
         if (!rhs[m] || !x[m]) return fail(hs[0], FTGCR_E_INVALID, "rhs or x is NULL");

@@ -245,3 +245,30 @@ def test_o160_51_levels_mixed(ft, oracle_mod):
     true = oracle_mod.OctOracle(pb).true_residual(x.cpu().numpy().ravel(), rhs)
     _say(f"O160 mixed: {st['steps_executed']} inner steps, {st['refinements']} refinements, true {true:.2e}")
     assert true <= 1.01e-8, true
+
+
+def test_batch_of_octahedral_members(ft, oracle_mod):
+    """O_N members of different sizes, one with a fault, in one batched
+    launch sequence: every member as the oracle (decisions, steps +-1, x
+    within 1e-10 at equal step counts); a batch mixing meshes is refused."""
+    pbs = [OctProblem(16, 8, hill_amp=0.7), OctProblem(8, 6, hill_lon=1.0), OctProblem(24, 9, hill_amp=0.4)]
+    rhs = [np.random.default_rng(70 + m).uniform(-1.0, 1.0, pb.n) for m, pb in enumerate(pbs)]
+    plans = [[FaultEvent(6, "r", 62, idx=np.array([321]))], [], [FaultEvent(4, "ap", 62, idx=np.array([9]))]]
+    solvers = [ft.Solver(pb, kmax=4) for pb in pbs]
+    _say("octahedral batch of", len(pbs))
+    xs, sts = ft.solve_batch(solvers, rhs, tols=[1e-10] * len(pbs), k=4, plans=plans)
+    for m, pb in enumerate(pbs):
+        o = oracle_mod.OctOracle(pb)
+        _, so, logo, _ = o.solve(rhs[m], tol=1e-10, k=4, plan=plans[m])
+        st = sts[m]
+        assert st["status"] == ft.CONVERGED, (m, st)
+        assert _decisions(st["log"]) == _decisions(logo), m
+        assert abs(st["steps_executed"] - so["steps_executed"]) <= 1, m
+        xe, _, _, _ = o.solve(rhs[m], tol=1e-13, k=4, plan=plans[m], max_steps=st["steps_executed"])
+        err = _rel(xs[m].cpu().numpy(), xe)
+        assert err <= 1e-10, (m, err)
+    c = ft.Solver(I.Problem(32, 16, 4), kmax=4)
+    with pytest.raises(ft.FtgcrError):
+        ft.solve_batch([solvers[0], c], [rhs[0], I.rhs(I.Problem(32, 16, 4), 1)], k=4)
+    for s in solvers + [c]:
+        s.close()
