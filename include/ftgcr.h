@@ -275,7 +275,8 @@ ftgcr_status ftgcr_set_stream(ftgcr_handle* h, void* hip_stream);
 /* Device workspace the caller must provide (bytes), for the handle's kmax:
  * the working vectors of Algorithm 1 in the storage precision -- the
  * directions p^l and their images L(p^l) with their backup copies (the
- * saved state of Section 2), three residual buffers and e = P^{-1} r -- one
+ * saved state of Section 2), three residual buffers and e = P^{-1} r, on
+ * the octahedral mesh also L(e) -- one
  * FP64 iterate buffer, block partial sums and the residual history (for
  * FT-GMRES the k+1 basis vectors, k preconditioned vectors and the
  * backup).  0 when h is NULL. */

@@ -253,7 +253,9 @@ Layout layout(const ftgcr_handle* h)
     L.xvec = align256(n * sizeof(double));
     L.part = align256((size_t)part_stride(h) * NV_MAX * sizeof(double));
     L.hist = align256((size_t)std::max<long long>(h->opt.hist_cap, 1) * sizeof(double));
-    L.total = (size_t)(2 * (h->kmax + 1) + 4) * L.vec + L.xvec + L.part + L.hist;
+    // P, AP (kmax + 1 each), three r, e, and on the octahedral mesh L(e)
+    const int nvec = 2 * (h->kmax + 1) + 4 + (h->geo.mesh == FTGCR_MESH_OCTAHEDRAL ? 1 : 0);
+    L.total = (size_t)nvec * L.vec + L.xvec + L.part + L.hist;
     return L;
 }
 
@@ -269,6 +271,10 @@ Inst<T> make_inst(const ftgcr_handle* h, const double* rhs, double* x, void* ws)
     for (int l = 0; l <= h->kmax; ++l) { in.AP[l] = (T*)p; p += L.vec; }
     for (int q = 0; q < 3; ++q) { in.R[q] = (T*)p; p += L.vec; }
     in.E = (T*)p; p += L.vec;
+    if (h->geo.mesh == FTGCR_MESH_OCTAHEDRAL) {
+        in.LE = (T*)p;
+        p += L.vec;
+    }
     in.X[0] = x;
     in.X[1] = (double*)p; p += L.xvec;
     in.part = (double*)p; p += L.part;

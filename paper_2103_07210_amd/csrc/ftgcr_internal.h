@@ -152,6 +152,10 @@ struct Inst {
     T* AP[KMAX + 1];
     T* R[3];
     T* E;
+    // octahedral mesh: L(e) of the step, stored by the dots pass and read by
+    // the direction pass instead of a second indirect stencil (null on the
+    // lat-lon mesh)
+    T* LE;
     double* X[2];            // X[0]: caller's x, X[1]: workspace
     const double* rhs;
     SolveState* st;

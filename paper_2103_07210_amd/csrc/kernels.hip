@@ -1536,8 +1536,15 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil_dots(Table<T> tb, int sp
     double le[KC];
     stencil_m<T, KC, MESH>(in.g, in.E, ps, le);
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk)
-        if (!(ps.col_ok && ps.k0 + kk < nz)) le[kk] = 0.0;
+    for (int kk = 0; kk < KC; ++kk) {
+        const bool ok = ps.col_ok && ps.k0 + kk < nz;
+        // octahedral mesh: L(e) kept for the direction pass (exact in T: the
+        // stencil rounds to T's precision, so the direction pass starts from
+        // the same value as if it had formed L(e) itself)
+        if constexpr (MESH == FTGCR_MESH_OCTAHEDRAL)
+            if (ok) in.LE[c0 + plane * (ps.k0 + kk)] = (T)le[kk];
+        if (!ok) le[kk] = 0.0;
+    }
     // every <L(e), L(p^l)>, one uniform branch per l; the loads of term
     // l + 1 are issued before term l's values are used (a two-stage
     // pipeline), so the terms cost one memory round trip together, not one
@@ -1684,8 +1691,24 @@ __global__ __launch_bounds__(ST_THREADS) void k_dir_update(Table<T> tb, int init
     const long long plane = (long long)in.g.ncols;
     const long long c0 = (long long)ps.i + (long long)in.g.nx * ps.j;
     double a[KC], p[KC], xa[KC], r[KC];
-    // p starts from e: the stencil's own centre values (no second load)
-    stencil_m<T, KC, MESH>(in.g, in.E, ps, a, p);
+    // p starts from e: the stencil's own centre values (no second load).
+    // On the octahedral mesh the step's dots pass has stored L(e): e and
+    // L(e) are loaded instead of gathering six neighbours again (the first
+    // direction of a solve or round, with no dots pass before it, forms it)
+    bool formed = false;
+    if constexpr (MESH == FTGCR_MESH_OCTAHEDRAL) {
+        if (!init) {
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const int kq = (ps.k0 + kk > nz - 1) ? nz - 1 : ps.k0 + kk;
+                const long long c = c0 + plane * kq;
+                p[kk] = (double)in.E[c];
+                a[kk] = (double)in.LE[c];
+            }
+            formed = true;
+        }
+    }
+    if (!formed) stencil_m<T, KC, MESH>(in.g, in.E, ps, a, p);
     // r is needed only for the next beta's products at the end: binary32
     // loads it there (the registers it frees give that kernel a sixth wave
     // per SIMD); FP64 loads it with the iterate (there a late load is
