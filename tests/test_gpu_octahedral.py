@@ -215,6 +215,20 @@ def test_mixed_reaches_true_residual(ft, oracle_mod, case):
     assert err <= 2e-5, err
 
 
+def test_mixed_without_preconditioner(ft, oracle_mod):
+    """The mixed form on O_N with P = I (binary32 copy pass, binary32
+    indirect stencil): the FP64 true residual meets the tolerance."""
+    pb = OctProblem(16, 8, hill_amp=0.7)
+    rhs = np.random.default_rng(13).uniform(-1.0, 1.0, pb.n)
+    s = ft.Solver(pb, "mixed", kmax=4, precond="none")
+    _say("octahedral mixed, P = I")
+    x, st = s.solve(rhs, tol=1e-8, k=4)
+    s.close()
+    assert st["status"] == ft.CONVERGED
+    true = oracle_mod.OctOracle(pb).true_residual(x.cpu().numpy().ravel(), rhs)
+    assert true <= 1.001e-8, true
+
+
 def test_mixed_detects_r_fault(ft, oracle_mod):
     """A binary32 exponent flip (bit 30) of every 7th entry of r at step 5
     of a mixed O_N solve is caught at that step, and the solve still meets
