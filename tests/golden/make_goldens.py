@@ -5,7 +5,7 @@ rendering of Algorithm 1) run on the seeded inputs of
 paper_2103_07210_amd/inputs.py; nothing comes from the GPU library.  The GPU
 tests (tests/test_gpu_goldens.py) compare the HIP path against these files.
 
-  python tests/golden/make_goldens.py [c2] [c3] [c5] [stag] [--jobs 7]
+  python tests/golden/make_goldens.py [c2] [c3] [c5] [o160] [stag] [--jobs 7]
 
 Targets (each writes <name>.json with the solve outcomes and decision logs,
 and <name>.npz with float arrays: residual histories, the sampled entries of
@@ -18,6 +18,9 @@ x and their flat indices):
   c3    512x256x64, k = 4, tol 1e-8, FP64, fault-free.
   c5    1024x512x96, k = 4, tol 1e-8, FP64, fault-free and with the 10%
         contiguous block of r flipped at bit 62 in step 10.
+  o160  the paper's O160 with 51 levels (Section 3, Table 1), k = 5 as in
+        the paper's runs, tol 1e-8, FP64, fault-free and with the same 10%
+        block fault (x sampled uniformly).
   stag  the stagnating right-hand sides of the 8x4x3 test (<r, A P^-1 r> = 0
         up to round-off): the oracle's own spread of executed steps when the
         right-hand side (1e-15 relative) or the coefficients (1e-15 relative
@@ -50,7 +53,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from oracle.oracle import Oracle  # noqa: E402
+from oracle.oracle import OctOracle, Oracle  # noqa: E402
 from paper_2103_07210_amd import inputs as I  # noqa: E402
 
 
@@ -192,6 +195,42 @@ def make_big(names, jobs: int):
         _write(f"{name}_fp64", meta, **arrays)
 
 
+# --- O160 x 51 levels ---------------------------------------------------------
+
+O160_K = 5
+
+
+def _o160(with_fault):
+    pb = I.O160
+    rhs = I.rhs(pb, I.SEEDS["c3_rhs"])
+    plan = I.block_plan(pb, step=10, vec="r", fraction=0.1, bit=62, seed=I.SEEDS["c5_plan"]) if with_fault else []
+    t0 = time.time()
+    x, st, log, hist = OctOracle(pb).solve(rhs, tol=BIG_TOL, k=O160_K, plan=plan)
+    idx = sample_indices(pb, 16384, 16001, structured=False)
+    rec = outcome(st, log)
+    rec.update(x_summary(x))
+    rec["plan"] = plan_json(plan)
+    rec["oracle_seconds"] = time.time() - t0
+    print(f"o160 fault={with_fault}: {st['steps_executed']} steps, {time.time() - t0:.0f} s", flush=True)
+    return with_fault, rec, hist, idx, x.reshape(-1)[idx]
+
+
+def make_o160(jobs: int):
+    pb = I.O160
+    with mp.Pool(min(jobs, 2)) as pool:
+        res = pool.map(_o160, [False, True])
+    meta = {"mesh": "octahedral", "N": pb.N, "nz": pb.nz, "k": O160_K, "tol": BIG_TOL,
+            "rhs_seed": I.SEEDS["c3_rhs"]}
+    arrays = {}
+    for wf, rec, hist, idx, xv in res:
+        tag = "fault" if wf else "clean"
+        meta[tag] = rec
+        arrays[f"hist_{tag}"] = hist
+        arrays["idx"] = idx
+        arrays[f"x_{tag}"] = xv
+    _write("o160_fp64", meta, **arrays)
+
+
 # --- stagnation spread -------------------------------------------------------
 
 STAG_TRIALS = 300
@@ -261,7 +300,7 @@ def _write(name: str, meta: dict, **arrays):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("targets", nargs="*", default=["stag", "c2", "c3", "c5"])
+    ap.add_argument("targets", nargs="*", default=["stag", "c2", "c3", "c5", "o160"])
     ap.add_argument("--jobs", type=int, default=max(1, (os.cpu_count() or 2) - 1))
     args = ap.parse_args()
     if "stag" in args.targets:
@@ -269,6 +308,8 @@ def main():
     big = [t for t in ("c3", "c5") if t in args.targets]
     if big:
         make_big(big, args.jobs)
+    if "o160" in args.targets:
+        make_o160(args.jobs)
     if "c2" in args.targets:
         make_c2(args.jobs)
 
