@@ -1,7 +1,7 @@
 """Fault campaigns on the GPU solver: per-run outcome records and the
 summaries the paper reports (Section 3, Tables 2-3).
 
-  python -m paper_2103_07210_amd.campaign [--count 200] [--grid 256,128,32] [--k 4]
+  python -m paper_2103_07210_amd.campaign [--count 200] [--grid 256,128,32 | O40x51] [--k 4]
   python -m paper_2103_07210_amd.campaign --model paper [--prob 0.02]
          [--loss 4e-6,4e-4,2e-3,0.01,0.05,0.2] [--procs 36] [--count 100] [--k 5]
          [--bits uniform|finite]
@@ -140,6 +140,20 @@ def summarize_paper(records: Sequence[Dict], clean_steps: int, clean_cycles: int
     return out
 
 
+def parse_grid(text: str):
+    """'nlon,nlat,nz' (lat-lon) or 'O<N>' / 'O<N>x<nz>' (octahedral, 51
+    levels unless given, as in the paper's Table 1)."""
+    from . import inputs as I
+    if text[:1] in ("O", "o"):
+        n, _, nz = text[1:].partition("x")
+        return I.OctProblem(int(n), int(nz) if nz else 51)
+    return I.Problem(*[int(v) for v in text.split(",")])
+
+
+def grid_label(pb) -> list:
+    return [f"O{pb.N}", pb.nz] if hasattr(pb, "N") else [pb.nx, pb.ny, pb.nz]
+
+
 def main():
     from . import inputs as I
     ap = argparse.ArgumentParser()
@@ -155,13 +169,13 @@ def main():
     ap.add_argument("--bits", choices=("uniform", "finite"), default="uniform",
                     help="paper model: which bits a flip may hit (all 64, or all but the top exponent bit)")
     args = ap.parse_args()
-    pb = I.Problem(*[int(v) for v in args.grid.split(",")])
+    pb = parse_grid(args.grid)
     import torch
     torch.cuda.set_device(0)
     if args.model == "config":
         plans = I.campaign_plans(pb, count=args.count, seed0=I.SEEDS["c2_plan0"])
         records, summary, _ = run(pb, plans, k=args.k, tol=args.tol)
-        summary["grid"] = [pb.nx, pb.ny, pb.nz]
+        summary["grid"] = grid_label(pb)
         summary["k"] = args.k
         print(json.dumps(summary), flush=True)
         return
@@ -170,7 +184,7 @@ def main():
         records, _, st_clean = run(pb, plans, k=args.k, tol=args.tol, rhs_seed=I.SEEDS["c2_rhs"],
                                    cap_factor=args.cap)
         summary = summarize_paper(records, st_clean["steps_executed"], st_clean["cycles"])
-        summary.update({"grid": [pb.nx, pb.ny, pb.nz], "k": args.k, "prob": args.prob,
+        summary.update({"grid": grid_label(pb), "k": args.k, "prob": args.prob,
                         "data_loss_percent": 100.0 * loss, "procs": args.procs, "bits": args.bits})
         print(json.dumps(summary), flush=True)
 

@@ -182,8 +182,9 @@ def block_plan(problem: Problem, step: int = 10, vec: str = "r", fraction: float
 def process_entries(problem: Problem, procs: int, rank: int) -> np.ndarray:
     """Canonical indices of the entries one of `procs` processes would own
     under a horizontal decomposition into bands of whole columns (column
-    index j * nx + i split into `procs` contiguous ranges, all levels)."""
-    ncols = problem.nx * problem.ny
+    index j * nx + i, or the O_N point index, split into `procs` contiguous
+    ranges, all levels)."""
+    ncols = problem.points if isinstance(problem, OctProblem) else problem.nx * problem.ny
     lo = (ncols * rank) // procs
     hi = (ncols * (rank + 1)) // procs
     cols = np.arange(lo, hi, dtype=np.int64)

@@ -47,3 +47,23 @@ def test_summarize_counts_detections_and_extra_steps():
     assert s["bitwise_equal_to_fault_free"] == 2
     assert s["roft_percent"] == pytest.approx(100 * ((110 + 100 + 101) / 3 - (102 + 100 + 104) / 3) / 100)
     assert s["detection_rate_by_vector"] == {"r": 1.0, "x": 0.0, "ap": 1.0}
+
+
+def test_octahedral_process_bands_and_grid_text():
+    """On O_N a process owns a contiguous range of points (latitude bands of
+    the ring-by-ring numbering) at every level; the bands partition the
+    mesh.  'O40' names the paper's O40 with its 51 levels (Table 1)."""
+    import numpy as np
+    from paper_2103_07210_amd import inputs as I
+    from paper_2103_07210_amd.campaign import grid_label, parse_grid
+    pb = I.OctProblem(4, 3)
+    procs = 5
+    owned = np.concatenate([I.process_entries(pb, procs, r) for r in range(procs)])
+    assert np.array_equal(np.sort(owned), np.arange(pb.n))
+    band = I.process_entries(pb, procs, 2)
+    pts = np.unique(band % pb.points)
+    assert pts.size * pb.nz == band.size and np.all(np.diff(pts) == 1)
+    o40 = parse_grid("O40")
+    assert (o40.N, o40.nz, o40.n) == (40, 51, 399840)
+    assert grid_label(parse_grid("O16x8")) == ["O16", 8]
+    assert grid_label(parse_grid("64,32,8")) == [64, 32, 8]
