@@ -3,8 +3,8 @@ fault-plan staging in the library's device scratch) against ftgcr_solve on
 the same handle and inputs: the same kernels in the same order, so the
 results are bitwise equal.  Two calls in a row, the second on a smaller
 grid (the scratch keeps the first call's contents); a mixed-precision
-handle; and a grid whose workspace exceeds the scratch is refused with a
-message before anything runs."""
+handle; the octahedral mesh; and a grid whose workspace exceeds the scratch
+is refused with a message before anything runs."""
 import numpy as np
 import pytest
 
@@ -63,6 +63,18 @@ def test_noalloc_mixed(ft):
     pb = Problem(64, 32, 8)
     _say("noalloc 64x32x8 mixed")
     _same(ft, pb, "mixed", 3, 1e-8, [FaultEvent(12, "r", 30, idx=np.array([200]))], 1)
+
+
+def test_noalloc_octahedral(ft):
+    """On O_N (whose workspace also holds the stored L(e)), FP64 with an r
+    and an e fault, then the mixed form."""
+    pb = I.OctProblem(16, 8, hill_amp=0.7)
+    plan = [FaultEvent(5, "r", 62, idx=np.array([321])), FaultEvent(9, "e", 62, idx=np.arange(0, pb.n, 97))]
+    _say("noalloc O16x8 fp64 with faults")
+    st = _same(ft, pb, "fp64", 4, 1e-10, plan, 5)
+    assert st["events_applied"] == 2 and st["detections"] >= 1
+    _say("noalloc O16x8 mixed")
+    _same(ft, pb, "mixed", 4, 1e-8, [], 6)
 
 
 def test_noalloc_rejects_grid_beyond_scratch(ft):
