@@ -1049,7 +1049,8 @@ ftgcr_status gm_solve_impl(ftgcr_handle* h, const double* rhs, double* x, double
     HIP_TRY(h, hipStreamSynchronize(s));
     const GmInst* d = h->gm_inst;
     // geometry and the column grid of the two-lane FP64 column kernel
-    const Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond};
+    const Table<double> tb{h->inst_dbg, h->blk0, h->blk0 + 2, h->blk0 + 4, 1, h->geo.mesh, h->precond,
+                           full_columns(h->geo.ncols, h->geo.nz, h->H) ? 1 : 0};
     const int nblk_col = (h->geo.ncols + COLS_PER_BLOCK - 1) / COLS_PER_BLOCK;
     const int nst = h->nblk_st, kc = h->kc;
     GmState* hs = h->gm_host;

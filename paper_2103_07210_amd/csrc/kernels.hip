@@ -1165,7 +1165,7 @@ __device__ __forceinline__ void update_thomas_body(Table<T> tb, const T* dbg_in,
             // the compiler moves all rows' eliminations after all the
             // stores, holding every row's values at once
             if constexpr (FULL) {
-                if (mode == MODE_STEP) *rw = sv;
+                if (mode == MODE_STEP || mode == MODE_GM) *rw = sv;
                 acc_new = fma(v, v, acc_new);
                 acc_st = fma(rp, rp, acc_st);
             } else if (mine && valid) {
@@ -1275,6 +1275,13 @@ template <int H>
 __global__ __launch_bounds__(COL_THREADS) void k_update_thomas_gm(Table<double> tb, const GmInst* gm)
 {
     update_thomas_body<double, H, MODE_GM, false>(tb, nullptr, nullptr, gm);
+}
+
+template <int H>
+__global__ __launch_bounds__(COL_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_update_thomas_gm_full(
+    Table<double> tb, const GmInst* gm)
+{
+    update_thomas_body<double, H, MODE_GM, true>(tb, nullptr, nullptr, gm);
 }
 
 // The binary32 column pass with one lane per column (256 columns per
@@ -2119,6 +2126,7 @@ void Launch<T>::update_thomas(const Table<T>& tb, int total, int H, int mode, hi
             case 8: FTGCR_T1(8) break;
             case 16: FTGCR_T1(16) break;
             case 24: FTGCR_T1(24) break;
+            case 28: FTGCR_T1(28) break;
             default: FTGCR_T1(32) break;
             }
 #undef FTGCR_T1
@@ -2891,7 +2899,12 @@ void GmLaunch::precond(const Table<double>& tb, const GmInst* gi, int nblk_col, 
                            (const double*)nullptr, (double*)nullptr, gi, COLS_PER_BLOCK);
         return;
     }
-    FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas_gm<HV>), dim3(nblk_col), dim3(COL_THREADS), 0, s, tb, gi));
+    if (tb.full)
+        FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas_gm_full<HV>), dim3(nblk_col), dim3(COL_THREADS), 0, s,
+                                             tb, gi))
+    else
+        FTGCR_H_SWITCH(H, hipLaunchKernelGGL((k_update_thomas_gm<HV>), dim3(nblk_col), dim3(COL_THREADS), 0, s, tb,
+                                             gi))
 }
 
 void GmLaunch::stencil(const GmInst* gi, int nblk, int kc, int dots, int mesh, hipStream_t s)
